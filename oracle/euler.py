@@ -1,0 +1,87 @@
+"""Strong-form nodal DG right-hand side of the compressible Euler equations
+(oracle, FP64).  Test infrastructure only (see the package docstring).
+
+The paper solves the Euler equations with nodal DG and explicit RK4 on a
+periodic isentropic vortex (Sec. 5.2) and gives no formula; this is the
+textbook strong form (Hesthaven & Warburton) read as follows:
+
+  q = (rho, m_x, m_y, m_z, E),  p = (gamma - 1)(E - |m|^2 / (2 rho)),
+  c = sqrt(gamma p / rho),
+  F_d(q) = (m_d, m_x m_d / rho + p delta_xd, m_y m_d / rho + p delta_yd,
+            m_z m_d / rho + p delta_zd, (E + p) m_d / rho)
+
+  volume:   vol_i = sum_{a in r,s,t} sum_j D_a[i, j] G_{a,j},
+            G_{a,j} = sum_d (da/dx_d) F_d(q_j)
+  surface:  at face node (f, m) with own node Fmask[f][m] (q-) and matched
+            neighbour node (q+), outward unit normal n, local Lax-Friedrichs
+            speed lam = max(|u-.n| + c-, |u+.n| + c+),
+            Delta = Fscale_f [ 1/2 n.(F(q-) - F(q+)) - 1/2 lam (q- - q+) ]
+  rhs_i = -vol_i + sum_{(f, m)} LIFT[i, (f, m)] Delta_{(f, m)}.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def _fluxes(q, gamma):
+    rho, mx, my, mz, E = q
+    u, v, w = mx / rho, my / rho, mz / rho
+    p = (gamma - 1.0) * (E - 0.5 * (mx * u + my * v + mz * w))
+    Fx = np.stack([mx, mx * u + p, my * u, mz * u, (E + p) * u])
+    Fy = np.stack([my, mx * v, my * v + p, mz * v, (E + p) * v])
+    Fz = np.stack([mz, mx * w, my * w, mz * w + p, (E + p) * w])
+    c = np.sqrt(gamma * p / rho)
+    return (Fx, Fy, Fz), (u, v, w), c
+
+
+def rhs(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: float = GAMMA,
+        elems=None, split: bool = False):
+    """Euler RHS for q[5][E][Np].
+
+    elems: optional index array; only those elements' RHS rows are computed
+    (their neighbours' traces are read from q).  Returns rhs[5][len(elems)][Np]
+    (or [5][E][Np]).  With split=True returns (rhs, volume_part, surface_part).
+    """
+    E = q.shape[1]
+    idx = np.arange(E) if elems is None else np.asarray(elems, dtype=np.int64)
+    qe = q[:, idx, :]
+    (Fx, Fy, Fz), _, _ = _fluxes(qe, gamma)
+    rx = geo["rst_x"][idx]  # [n, (r,s,t), x]
+    vol = np.zeros_like(qe)
+    for a, D in enumerate((ops["Dr"], ops["Ds"], ops["Dt"])):
+        G = rx[None, :, a, 0, None] * Fx + rx[None, :, a, 1, None] * Fy + rx[None, :, a, 2, None] * Fz
+        vol += G @ D.T
+
+    Nfp = ops["Nfp"]
+    fm = ops["Fmask"].reshape(-1)  # face-major own node of each face node
+    qM = qe[:, :, fm]
+    qP = q[:, conn["mapP_elem"][idx], conn["mapP_node"][idx]]
+    n = np.repeat(geo["normals"][idx], Nfp, axis=1)  # [n, 4Nfp, 3]
+    Fs = np.repeat(geo["Fscale"][idx], Nfp, axis=1)  # [n, 4Nfp]
+    (FxM, FyM, FzM), (uM, vM, wM), cM = _fluxes(qM, gamma)
+    (FxP, FyP, FzP), (uP, vP, wP), cP = _fluxes(qP, gamma)
+    nx, ny, nz = n[..., 0], n[..., 1], n[..., 2]
+    FnM = nx * FxM + ny * FyM + nz * FzM
+    FnP = nx * FxP + ny * FyP + nz * FzP
+    lam = np.maximum(np.abs(uM * nx + vM * ny + wM * nz) + cM, np.abs(uP * nx + vP * ny + wP * nz) + cP)
+    delta = Fs * (0.5 * (FnM - FnP) - 0.5 * lam * (qM - qP))
+    surf = delta @ ops["LIFT"].T
+    out = -vol + surf
+    if split:
+        return out, vol, surf
+    return out
+
+
+def max_wave_speed(q: np.ndarray, gamma: float = GAMMA) -> float:
+    """max over nodes of |u| + c."""
+    _, (u, v, w), c = _fluxes(q, gamma)
+    return float(np.max(np.sqrt(u * u + v * v + w * w) + c))
+
+
+def cfl_dt(ops: dict, geo: dict, q: np.ndarray, cfl: float = 0.2, gamma: float = GAMMA) -> float:
+    """dt = CFL / (lambda_max (p+1)^2 max Fscale), the step-size reading used
+    for all runs (computed once from the initial state)."""
+    p = ops["p"]
+    return cfl / (max_wave_speed(q, gamma) * (p + 1) ** 2 * float(np.max(geo["Fscale"])))

@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs for the DG right-hand-side path.
+
+This module produces *inputs only*: periodic tetrahedral box meshes (vertex
+coordinates and global vertex ids) and initial states evaluated at caller-given
+node coordinates.  It contains none of the discretisation's arithmetic (no node
+sets, operators, geometric factors, fluxes or time stepping), so that the CPU
+oracle and the GPU library can both be fed from it without sharing any of the
+method.
+
+Workloads (the paper's periodic isentropic-vortex Euler benchmark, Sec. 5.2,
+stands in for by these synthetic meshes and states):
+
+* box [0, L]^3 split into n^3 cubes, each cut into 6 Kuhn tetrahedra along the
+  main diagonal; vertices jittered per unique periodic vertex by U[-a h, a h]
+  per component (h = L/n), which keeps the mesh periodic and its volume L^3;
+* isentropic vortex (strength beta, free-stream Mach 0.5 along +x, column along
+  z) on an ideal gas, optionally with a smooth periodic entropy perturbation of
+  the density;
+* constant states and "entropy waves" (constant velocity and pressure,
+  arbitrary density) used by invariance tests.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+# Kuhn (Freudenthal) subdivision: one tetrahedron per permutation of the axes,
+# walking from the cube's lower corner to its upper corner.
+_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+_PERM_SIGN = (1, -1, -1, 1, 1, -1)
+
+
+def kuhn_mesh(dims, lengths, jitter: float = 0.05, seed: int = 0):
+    """Periodic box mesh of nx*ny*nz cubes (cells) x 6 tets.
+
+    dims = (nx, ny, nz) cells, lengths = (Lx, Ly, Lz).  Returns
+    ``(elem_xyz, elem_vid)``:
+      elem_xyz  float64 [E, 4, 3]  unwrapped vertex coordinates (positive volume)
+      elem_vid  int64   [E, 4]     global vertex ids; periodic images share ids
+    Element id = 6 * (i + nx * (j + ny * k)) + perm, perm in the order
+    xyz, xzy, yxz, yzx, zxy, zyx.  Tets of odd permutations swap their last two
+    vertices so every element is positively oriented.  Each unique periodic
+    vertex is moved by U[-jitter h_d, jitter h_d] in each component d.
+    """
+    nx, ny, nz = (int(v) for v in dims)
+    if min(nx, ny, nz) < 1:
+        raise ValueError("cell counts must be >= 1")
+    h = np.array([lengths[0] / nx, lengths[1] / ny, lengths[2] / nz])
+    rng = np.random.default_rng(seed)
+    jit = rng.uniform(-1.0, 1.0, size=(nx * ny * nz, 3)) * (jitter * h)[None, :]
+
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ijk = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)  # cell c = i + nx*(j + ny*k)
+    E = 6 * nx * ny * nz
+    elem_lat = np.zeros((E, 4, 3), dtype=np.int64)
+    for pi, perm in enumerate(_PERMS):
+        p0 = ijk.copy()
+        p1 = p0.copy()
+        p1[:, perm[0]] += 1
+        p2 = p1.copy()
+        p2[:, perm[1]] += 1
+        p3 = p2.copy()
+        p3[:, perm[2]] += 1
+        verts = (p0, p1, p2, p3) if _PERM_SIGN[pi] > 0 else (p0, p1, p3, p2)
+        for v in range(4):
+            elem_lat[pi::6, v, :] = verts[v]
+    wrapped = elem_lat % np.array([nx, ny, nz])
+    elem_vid = wrapped[..., 0] + nx * (wrapped[..., 1] + ny * wrapped[..., 2])
+    elem_xyz = elem_lat.astype(np.float64) * h[None, None, :] + jit[elem_vid]
+    return elem_xyz, elem_vid.astype(np.int64)
+
+
+def kuhn_box_mesh(n: int, L: float = 10.0, jitter: float = 0.05, seed: int = 0):
+    """Cubic periodic box [0, L]^3 of n^3 cubes x 6 tets (see kuhn_mesh)."""
+    return kuhn_mesh((n, n, n), (L, L, L), jitter, seed)
+
+
+def vortex_slab_mesh(n: int, L: float = 10.0, nz: int = 3, jitter: float = 0.05, seed: int = 0):
+    """n x n x nz cubes of side L/n: a thin periodic slab for the z-independent
+    vortex, so that in-plane resolution can be raised cheaply."""
+    h = L / n
+    return kuhn_mesh((n, n, nz), (L, L, nz * h), jitter, seed)
+
+
+def _wrap(d, L):
+    return (d + 0.5 * L) % L - 0.5 * L
+
+
+def primitive_to_conserved(rho, u, v, w, p, gamma=GAMMA):
+    """Ideal-gas conserved variables (rho, rho u, rho v, rho w, E)."""
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E])
+
+
+def vortex_primitive(xyz, t=0.0, beta=5.0, center=(5.0, 5.0), mach=0.5, L=10.0, gamma=GAMMA, radius=1.0):
+    """Isentropic vortex (Shu 1998; Yee, Sandham & Djomehri 1999) in a periodic box.
+
+    rho_inf = p_inf = 1, free stream u_inf = mach * sqrt(gamma) along +x, column
+    along z, core radius ``radius`` (distances scaled by 1/radius).  The exact
+    solution at time t is the t = 0 field translated by u_inf * t (periodic
+    wrap, nearest image).  Returns (rho, u, v, w, p) arrays
+    shaped like ``xyz[..., 0]``.
+    """
+    uinf = mach * math.sqrt(gamma)
+    x = xyz[..., 0]
+    y = xyz[..., 1]
+    dx = _wrap(x - (center[0] + uinf * t), L) / radius
+    dy = _wrap(y - center[1], L) / radius
+    r2 = dx * dx + dy * dy
+    ex = np.exp(0.5 * (1.0 - r2))
+    u = uinf - beta / (2.0 * math.pi) * dy * ex
+    v = beta / (2.0 * math.pi) * dx * ex
+    w = np.zeros_like(x)
+    T = 1.0 - (gamma - 1.0) * beta * beta / (8.0 * gamma * math.pi * math.pi) * ex * ex
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho ** gamma
+    return rho, u, v, w, p
+
+
+def density_perturbation(seed: int, modes: int = 4, amplitude: float = 1e-2, kmax: int = 4):
+    """Seeded smooth periodic perturbation parameters: integer wave vectors in
+    {1..kmax}^3, non-negative weights summing to one, phases in [0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, kmax + 1, size=(modes, 3))
+    a = rng.uniform(0.0, 1.0, size=modes)
+    a = a / a.sum()
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=modes)
+    return {"k": k, "a": a, "phi": phi, "amplitude": amplitude}
+
+
+def apply_density_perturbation(rho, xyz, pert, L=10.0):
+    s = np.zeros_like(rho)
+    for m in range(len(pert["a"])):
+        arg = 2.0 * math.pi * (xyz @ pert["k"][m].astype(np.float64)) / L + pert["phi"][m]
+        s = s + pert["a"][m] * np.sin(arg)
+    return rho * (1.0 + pert["amplitude"] * s)
+
+
+def vortex_state(xyz, t=0.0, beta=5.0, center=(5.0, 5.0), L=10.0, pert=None, gamma=GAMMA, radius=1.0):
+    """Conserved state q[5][E][Np] of the (optionally perturbed) vortex at the
+    given node coordinates ``xyz[E][Np][3]``."""
+    rho, u, v, w, p = vortex_primitive(xyz, t=t, beta=beta, center=center, L=L, gamma=gamma, radius=radius)
+    if pert is not None:
+        rho = apply_density_perturbation(rho, xyz, pert, L=L)
+    return np.ascontiguousarray(primitive_to_conserved(rho, u, v, w, p, gamma))
+
+
+def constant_state(shape, rho=1.3, vel=(0.3, -0.2, 0.1), p=0.9, gamma=GAMMA):
+    one = np.ones(shape)
+    return np.ascontiguousarray(
+        primitive_to_conserved(rho * one, vel[0] * one, vel[1] * one, vel[2] * one, p * one, gamma))
+
+
+def entropy_wave_state(xyz, rho_fn, vel=(0.4, -0.25, 0.15), p=1.0, gamma=GAMMA):
+    """Constant velocity and pressure with density rho_fn(xyz)."""
+    rho = rho_fn(xyz)
+    one = np.ones_like(rho)
+    return np.ascontiguousarray(
+        primitive_to_conserved(rho, vel[0] * one, vel[1] * one, vel[2] * one, p * one, gamma))
+
+
+# Named workloads (mesh seed, perturbation seed) used by the tests and the bench.
+WORKLOADS = {
+    "vortex_p2_4cubed": dict(n=4, order=2, jitter=0.05, mesh_seed=1001, pert_seed=None),
+    "vortex_pert_p3_48cubed": dict(n=48, order=3, jitter=0.03, mesh_seed=1002, pert_seed=2002),
+}

@@ -1,0 +1,166 @@
+"""Pins of the oracle's Euler RHS against what the mathematics fixes:
+free-stream preservation, discrete conservation on a periodic mesh, the
+entropy-wave special case (every flux linear in rho), exact volume divergence
+of polynomial fluxes, the discrete divergence theorem, the Lax-Friedrichs
+dissipation identity, and convergence to the isentropic vortex (the paper's
+Sec. 5.2 benchmark) at the expected orders."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import euler as oe, lsrk, mesh as om, reference_element as re
+from paper_2512_17101_amd import workload as wl
+
+
+def _setup(p, n=4, jitter=0.05, seed=1001, L=10.0):
+    xyz, vid = wl.kuhn_box_mesh(n, L, jitter, seed)
+    ops = re.operators(p)
+    geo = om.geometry(xyz)
+    conn = om.connectivity(vid, p)
+    X = om.node_coordinates(xyz, ops["rst"])
+    return ops, geo, conn, X
+
+
+@pytest.fixture(scope="module", params=[1, 2, 3, 4])
+def mesh_p(request):
+    return _setup(request.param)
+
+
+def test_free_stream_preservation(mesh_p):
+    ops, geo, conn, X = mesh_p
+    q = wl.constant_state(X.shape[:2])
+    r = oe.rhs(ops, geo, conn, q)
+    S = oe.max_wave_speed(q) * np.abs(q).max() * geo["Fscale"].max()
+    assert np.abs(r).max() <= 1e-12 * S
+
+
+def test_discrete_conservation(mesh_p):
+    ops, geo, conn, X = mesh_p
+    pert = wl.density_perturbation(7)
+    q = wl.vortex_state(X, pert=pert)
+    r = oe.rhs(ops, geo, conn, q)
+    w = geo["J"][:, None] * (r @ ops["M"].T)  # J M rhs per element, per field
+    tot = w.sum(axis=(1, 2))
+    scale = np.abs(w).sum(axis=(1, 2))
+    assert np.all(np.abs(tot) <= 1e-13 * scale)
+
+
+def test_entropy_wave_linearity(mesh_p):
+    ops, geo, conn, X = mesh_p
+    vel = np.array([0.4, -0.25, 0.15])
+    rho_fn = lambda x: 1.0 + 0.3 * np.sin(2 * np.pi * x[..., 0] / 10) * np.cos(2 * np.pi * (x[..., 1] + 2 * x[..., 2]) / 10)
+    q = wl.entropy_wave_state(X, rho_fn, vel=tuple(vel))
+    r = oe.rhs(ops, geo, conn, q)
+    scale = np.abs(r[0]).max()
+    for d in range(3):
+        np.testing.assert_allclose(r[1 + d], vel[d] * r[0], atol=1e-12 * scale)
+    np.testing.assert_allclose(r[4], 0.5 * vel @ vel * r[0], atol=1e-12 * scale)
+
+
+def test_volume_term_exact_for_polynomial_density(mesh_p):
+    ops, geo, conn, X = mesh_p
+    p = ops["p"]
+    vel = np.array([0.4, -0.25, 0.15])
+    c = np.array([0.3, -0.2, 0.1])
+    rho_fn = lambda x: 2.0 + ((x @ c) / 10.0) ** p
+    grad = lambda x: p * ((x @ c) / 10.0) ** (p - 1) * (vel @ c) / 10.0
+    q = wl.entropy_wave_state(X, rho_fn, vel=tuple(vel))
+    _, vol, _ = oe.rhs(ops, geo, conn, q, split=True)
+    np.testing.assert_allclose(vol[0], grad(X), atol=1e-12 * max(1.0, np.abs(grad(X)).max()))
+
+
+def test_divergence_theorem_on_elements(mesh_p):
+    ops, geo, conn, X = mesh_p
+    p = ops["p"]
+    Nfp = ops["Nfp"]
+    E_mat = ops["E"]
+    for e in (0, 5, 77):
+        x = X[e]
+        u = np.stack([x[:, 0] ** p, (x[:, 1] * x[:, 2]) ** (p // 2) + x[:, 0], x[:, 2] ** max(p - 1, 1)], 1)
+        rx = geo["rst_x"][e]
+        div = sum(rx[a, d] * (D @ u[:, d]) for a, D in enumerate((ops["Dr"], ops["Ds"], ops["Dt"])) for d in range(3))
+        lhs = geo["J"][e] * np.ones(len(x)) @ ops["M"] @ div
+        rhs_ = 0.0
+        for f in range(4):
+            un = u[ops["Fmask"][f]] @ geo["normals"][e, f]
+            rhs_ += geo["sJ"][e, f] * np.ones(ops["Np"]) @ E_mat[:, f * Nfp:(f + 1) * Nfp] @ un
+        assert abs(lhs - rhs_) < 1e-11 * max(1.0, abs(lhs))
+
+
+def test_lax_friedrichs_dissipation_identity(mesh_p):
+    """Discontinuous density at rest (u = 0, p const): volume flux vanishes and
+    d/dt 1/2 int rho^2 = -1/4 sum_{K,f} sJ [rho]^T M_f (lambda [rho]) exactly
+    (each face counted from both sides)."""
+    ops, geo, conn, X = mesh_p
+    rng = np.random.default_rng(11)
+    rho_nodes = rng.uniform(0.8, 1.2, size=X.shape[:2])
+    q = wl.entropy_wave_state(X, lambda x: rho_nodes, vel=(0.0, 0.0, 0.0), p=1.0)
+    r = oe.rhs(ops, geo, conn, q)
+    Nfp = ops["Nfp"]
+    rho = q[0]
+    lhs = np.sum(geo["J"][:, None] * rho * (r[0] @ ops["M"].T))
+    rhoM = rho[:, ops["Fmask"].reshape(-1)]
+    rhoP = rho[conn["mapP_elem"], conn["mapP_node"]]
+    c = lambda rr: np.sqrt(1.4 * 1.0 / rr)
+    lam = np.maximum(c(rhoM), c(rhoP))
+    d = rhoM - rhoP
+    rhs_ = 0.0
+    for f in range(4):
+        Mf = ops["E"][ops["Fmask"][f], f * Nfp:(f + 1) * Nfp]  # face mass
+        sl = slice(f * Nfp, (f + 1) * Nfp)
+        rhs_ += np.sum(geo["sJ"][:, f] * np.einsum("em,mn,en->e", d[:, sl], Mf, lam[:, sl] * d[:, sl]))
+    assert lhs < 0
+    assert abs(lhs - (-0.25 * rhs_)) < 1e-12 * abs(lhs)
+
+
+def _slab(n, p):
+    xyz, vid = wl.vortex_slab_mesh(n, 10.0, 3, 0.05, 7)
+    ops = re.operators(p)
+    return ops, om.geometry(xyz), om.connectivity(vid, p), om.node_coordinates(xyz, ops["rst"])
+
+
+def _window_l2(ops, geo, X, e, T):
+    uinf = 0.5 * math.sqrt(1.4)
+    cen = X.mean(axis=1)
+    dx = (cen[:, 0] - (5 + uinf * T) + 5) % 10 - 5
+    dy = cen[:, 1] - 5
+    m = dx * dx + dy * dy < 2.5 ** 2
+    return math.sqrt(np.sum(geo["J"][m] * np.einsum("ei,ij,ej->e", e[m], ops["M"], e[m])))
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_vortex_rhs_consistency_order(p):
+    """rhs(interpolated exact vortex) -> exact time derivative at order ~p."""
+    errs = []
+    for n in (10, 20):
+        ops, geo, conn, X = _slab(n, p)
+        d = 1e-4
+        dqdt = (wl.vortex_state(X, t=d) - wl.vortex_state(X, t=-d)) / (2 * d)
+        r = oe.rhs(ops, geo, conn, wl.vortex_state(X))
+        errs.append(_window_l2(ops, geo, X, (r - dqdt)[0], 0.0))
+    assert math.log2(errs[0] / errs[1]) >= p - 0.5
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("p,bound", [(2, 5e-3), (3, 1e-3)])
+def test_vortex_convergence_order(p, bound):
+    """LSRK(5,4) + DG evolution of the isentropic vortex (core radius 1.5, an
+    exact Euler solution as well) converges at close to the p + 1/2 rate that
+    upwind-type DG guarantees on general meshes (pin: order >= p + 0.3, and a
+    small absolute error at the finer mesh)."""
+    T = 0.1
+    R = 1.5
+    errs = []
+    for n in (8, 16):
+        ops, geo, conn, X = _slab(n, p)
+        q = wl.vortex_state(X, radius=R)
+        dt = oe.cfl_dt(ops, geo, q, 0.4)
+        nst = int(math.ceil(T / dt))
+        dt = T / nst
+        f = lambda qq, tt: oe.rhs(ops, geo, conn, qq)
+        for s in range(nst):
+            q, _ = lsrk.lsrk_step(f, q, s * dt, dt)
+        errs.append(_window_l2(ops, geo, X, (q - wl.vortex_state(X, t=T, radius=R))[0], T))
+    assert math.log2(errs[0] / errs[1]) >= p + 0.3
+    assert errs[1] < bound

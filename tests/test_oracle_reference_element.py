@@ -1,0 +1,145 @@
+"""Pins of the oracle's reference element against closed forms and exact
+integrals (nodes: warp & blend reduces to LGL edge points and face centroids
+for p <= 3; operators: exactness on polynomials, Dirichlet integrals)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import reference_element as re
+
+VERTS = np.array([[-1.0, -1, -1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]])
+
+
+def _closed_form_nodes(p):
+    """Vertices, edge points at the LGL(p+1) parameters, face centroids (p=3),
+    listed in the lattice order t outer, s middle, r inner."""
+    lgl = {1: [-1, 1], 2: [-1, 0, 1], 3: [-1, -1 / math.sqrt(5), 1 / math.sqrt(5), 1]}[p]
+    out = []
+    for n in range(p + 1):
+        for m in range(p + 1 - n):
+            for q in range(p + 1 - n - m):
+                lam = np.array([p - n - m - q, q, m, n], dtype=float)  # lattice barycentrics * p
+                nz = np.nonzero(lam)[0]
+                if len(nz) == 1:
+                    out.append(VERTS[nz[0]])
+                elif len(nz) == 2:
+                    a, b = nz
+                    k = int(lam[b])  # position along edge a -> b
+                    x = lgl[k]
+                    out.append(VERTS[a] + (1 + x) / 2 * (VERTS[b] - VERTS[a]))
+                else:
+                    out.append(lam @ VERTS / p)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_nodes_closed_form(p):
+    np.testing.assert_allclose(re.nodes(p), _closed_form_nodes(p), atol=1e-14)
+
+
+def test_nodes_p3_edge_parameter():
+    x = re.nodes(3)
+    # node 1 lies on edge v1-v2 at r = -1/sqrt(5)
+    assert abs(x[1, 0] + 1 / math.sqrt(5)) < 1e-15
+
+
+def _bary(x):
+    return np.stack([-(1 + x.sum(1)) / 2, (1 + x[:, 0]) / 2, (1 + x[:, 1]) / 2, (1 + x[:, 2]) / 2], 1)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_nodes_count_and_symmetry(p):
+    x = re.nodes(p)
+    assert x.shape == (re.n_nodes(p), 3)
+    lam = _bary(x)
+    key = lambda L: np.array(sorted(map(tuple, np.round(L, 10))))
+    base = key(lam)
+    for perm in itertools.permutations(range(4)):
+        np.testing.assert_allclose(key(lam[:, perm]), base, atol=1e-10)
+
+
+def test_nodes_p4_edges_lgl_and_centroid():
+    x = re.nodes(4)
+    lam = _bary(x)
+    edge = np.sum(lam > 1e-12, axis=1) == 2
+    params = np.sort(np.unique(np.round((x[edge][:, 0])[np.abs(x[edge][:, 1] + 1) + np.abs(x[edge][:, 2] + 1) < 1e-12], 12)))
+    np.testing.assert_allclose(params, [-math.sqrt(3 / 7), 0.0, math.sqrt(3 / 7)], atol=1e-14)
+    interior = np.all(lam > 1e-12, axis=1)
+    np.testing.assert_allclose(x[interior], [[-0.5, -0.5, -0.5]], atol=1e-14)
+
+
+def _monomials(p):
+    return [(a, b, c) for a in range(p + 1) for b in range(p + 1 - a) for c in range(p + 1 - a - b)]
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_differentiation_exact_on_polynomials(p):
+    ops = re.operators(p)
+    r, s, t = ops["rst"].T
+    for (a, b, c) in _monomials(p):
+        u = r ** a * s ** b * t ** c
+        dr = a * r ** max(a - 1, 0) * s ** b * t ** c
+        ds = b * r ** a * s ** max(b - 1, 0) * t ** c
+        dt = c * r ** a * s ** b * t ** max(c - 1, 0)
+        for D, ex in ((ops["Dr"], dr), (ops["Ds"], ds), (ops["Dt"], dt)):
+            np.testing.assert_allclose(D @ u, ex, atol=2e-12 * max(1.0, np.abs(ex).max()))
+    for D in (ops["Dr"], ops["Ds"], ops["Dt"]):
+        assert np.abs(D.sum(axis=1)).max() < 1e-12
+
+
+def _dirichlet(exps, dim_measure, dim):
+    """int over a simplex of prod lambda_i^{e_i} = prod e_i! dim! |T| / (sum e + dim)!"""
+    num = math.prod(math.factorial(e) for e in exps) * math.factorial(dim) * dim_measure
+    return num / math.factorial(sum(exps) + dim)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_mass_matrix_exact_integrals(p):
+    ops = re.operators(p)
+    M = ops["M"]
+    assert np.allclose(M, M.T, atol=1e-15)
+    assert np.linalg.eigvalsh(M).min() > 0
+    assert abs(M.sum() - 4 / 3) < 1e-14
+    lam = _bary(ops["rst"])
+    rng = np.random.default_rng(0)
+    for _ in range(6):
+        e1 = rng.multinomial(p, [0.25] * 4) if p else np.zeros(4, int)
+        e2 = rng.multinomial(p, [0.25] * 4)
+        f = np.prod(lam ** e1, axis=1)
+        g = np.prod(lam ** e2, axis=1)
+        exact = _dirichlet(e1 + e2, 4 / 3, 3)
+        assert abs(f @ M @ g - exact) < 1e-14 * max(1.0, exact) + 1e-15
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_face_matrix_exact_integrals(p):
+    ops = re.operators(p)
+    E, Fmask, Nfp = ops["E"], ops["Fmask"], ops["Nfp"]
+    lam = _bary(ops["rst"])
+    faces = ((0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3))
+    rng = np.random.default_rng(1)
+    for f in range(4):
+        Ef = E[:, f * Nfp:(f + 1) * Nfp]
+        assert abs(Ef.sum() - 2.0) < 1e-13  # parametric face area
+        for _ in range(4):
+            e1 = rng.multinomial(p, [1 / 3] * 3)
+            e2 = rng.multinomial(p, [1 / 3] * 3)
+            lf = lam[:, faces[f]]
+            u = np.prod(lf ** e1, axis=1)
+            g = np.prod(lf ** e2, axis=1)
+            exact = _dirichlet(e1 + e2, 2.0, 2)
+            assert abs(u @ Ef @ g[Fmask[f]] - exact) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_lift_definition(p):
+    ops = re.operators(p)
+    np.testing.assert_allclose(ops["M"] @ ops["LIFT"], ops["E"], atol=1e-13)
+
+
+def test_fmask_p3():
+    ops = re.operators(3)
+    assert ops["Fmask"].tolist()[0] == list(range(10))
+    assert ops["Fmask"].tolist()[3] == [0, 4, 7, 9, 10, 13, 15, 16, 18, 19]
