@@ -1,0 +1,129 @@
+/*
+ * dg.h — C ABI of the MI355X nodal discontinuous-Galerkin right-hand-side library.
+ *
+ * The library evaluates the nodal DG semi-discretisation of the compressible
+ * Euler equations on affine tetrahedra and advances it with low-storage RK4:
+ * the per-element arrays of nodal unknowns the paper describes (Sec. 1,
+ * Fig. "dg_mesh"), the periodic isentropic-vortex Euler/RK4 benchmark of
+ * Sec. 5.2, and the bandwidth-bound low-order element kernels profiled in
+ * Sec. 5.4.  The paper prints no DG formula; the operations below follow the
+ * textbook nodal DG method (Hesthaven & Warburton), as stated per entry point.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns a dg_status; DG_OK is 0.  On failure a message is
+ *    available from dg_last_error() (thread-local, valid until the next call
+ *    on the same thread).  No C++ exception crosses this interface.
+ *  - State layout (field-major): q[nf][E][Np] FP64, contiguous, element e's
+ *    node i of field f at q[(f * E + e) * Np + i].  nf = 5 for Euler:
+ *    (rho, rho u, rho v, rho w, E_total).
+ *  - Node order inside an element: the equidistant lattice of order p walked
+ *    with t outermost, then s, then r innermost, each point moved by the
+ *    warp & blend map (Warburton 2006) and keeping its index.  Reference
+ *    vertices v1=(-1,-1,-1), v2=(1,-1,-1), v3=(-1,1,-1), v4=(-1,-1,1); faces
+ *    f0={t=-1}, f1={s=-1}, f2={r+s+t=-1}, f3={r=-1}.
+ *  - Device buffers (q, rhs, work) are caller-owned device memory, 8-byte
+ *    aligned at least (256-byte recommended); the library never frees them and
+ *    keeps no pointer past return.  Compute calls are asynchronous on the given
+ *    HIP stream (0 = the null stream); argument checks are synchronous.
+ *  - Handles (dg_mesh) own their device copies; dg_mesh_destroy frees them.
+ *    A handle is immutable after creation, so calls on different streams may
+ *    share it.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DG_OK = 0,
+  DG_ERR_ARG = 1,         /* null/misaligned pointer, size or enum out of range */
+  DG_ERR_MESH = 2,        /* non-positive Jacobian, unmatched or over-shared face */
+  DG_ERR_ALLOC = 3,       /* device or host allocation failed */
+  DG_ERR_HIP = 4,         /* a HIP runtime call failed (message carries its text) */
+  DG_ERR_NOCONV = 5,      /* iterative solve did not converge */
+  DG_ERR_NONFINITE = 6,   /* non-finite value detected */
+  DG_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+} dg_status;
+
+/* Precision of the element-local contractions (volume divergence and lift)
+ * only; pointwise fluxes, the face flux, the state and the RK update are FP64
+ * in every mode. */
+typedef enum { DG_FP64 = 0, DG_FP32 = 1, DG_SPLIT_BF16 = 2 } dg_precision;
+
+typedef struct {
+  int model;      /* 0 = Euler (ideal gas); other values are rejected */
+  double gamma;   /* ratio of specific heats, > 1 */
+} dg_params;
+
+typedef struct dg_mesh_s* dg_mesh;
+
+/* Reference-element tables of order p (1..4), computed on the host (no GPU
+ * needed).  Nodes and operators of the nodal basis as defined above:
+ *   rst   [Np][3]        node coordinates (r, s, t)
+ *   Dr,Ds,Dt [Np][Np]    Dr[i][j] = d l_j/dr at node i (row-major)
+ *   LIFT  [Np][4*Nfp]    M^{-1} E, columns face-major (f, m)
+ *   Fmask [4][Nfp]       ascending node indices on each face
+ * Any output pointer may be NULL.  Returns DG_ERR_ARG for p outside 1..4. */
+dg_status dg_reference_operators(int order, double* rst, double* Dr, double* Ds, double* Dt,
+                                 double* LIFT, int32_t* Fmask);
+
+/* Build a mesh handle on `device` from affine tetrahedra.
+ *   elem_xyz  host [n_elem][4][3]  vertex coordinates (periodic images given
+ *                                  unwrapped); the reference-to-physical map
+ *                                  x = -(1+r+s+t)/2 X1 + (1+r)/2 X2 + (1+s)/2 X3
+ *                                  + (1+t)/2 X4 must have J > 0
+ *   elem_vid  host [n_elem][4]     global vertex ids; faces match on the
+ *                                  sorted id triple, so periodic images must
+ *                                  share ids; every face must occur exactly twice
+ * Geometric factors, face connectivity (neighbour, neighbour face and vertex
+ * permutation per face) and the reference operators are computed on the host
+ * and copied to the device (synchronous).  Errors: DG_ERR_ARG (order not in
+ * 1..4, n_elem < 1 or > 2^27, null pointers, bad device), DG_ERR_MESH (J <= 0,
+ * unmatched face), DG_ERR_ALLOC / DG_ERR_HIP. */
+dg_status dg_mesh_create(int order, int64_t n_elem, const double* elem_xyz, const int64_t* elem_vid,
+                         int device, dg_mesh* out);
+dg_status dg_mesh_info(dg_mesh m, int64_t* n_elem, int* np, int* nfp);
+/* Physical node coordinates, host [n_elem][Np][3] (parity hook). */
+dg_status dg_mesh_nodes(dg_mesh m, double* xyz_host);
+/* Face-node map as seen by the library, host [n_elem][4*Nfp] each: neighbour
+ * element and neighbour volume-node index of every face node (parity hook). */
+dg_status dg_mesh_face_map(dg_mesh m, int64_t* nbr_elem, int32_t* nbr_node);
+dg_status dg_mesh_destroy(dg_mesh m);
+
+/* Strong-form nodal DG right-hand side of the Euler equations:
+ *   rhs = -sum_{a=r,s,t} D_a (sum_d da/dx_d F_d(q))
+ *         + LIFT * ( Fscale * [ 1/2 n.(F(q-) - F(q+)) - 1/2 lam (q- - q+) ] )
+ * with the local Lax-Friedrichs speed lam = max(|u-.n| + c-, |u+.n| + c+) at
+ * every face node.  q, rhs: device [5][E][Np] FP64 (must not alias).
+ * prec selects the contraction precision (DG_FP64 only in this build:
+ * others return DG_ERR_UNSUPPORTED).  Asynchronous on `stream`. */
+dg_status dg_rhs(dg_mesh m, const dg_params* prm, dg_precision prec, const double* q, double* rhs,
+                 hipStream_t stream);
+
+/* One step of Carpenter & Kennedy's five-stage fourth-order 2N-storage
+ * Runge-Kutta scheme:  res <- 0; for s = 1..5: res <- a_s res + dt RHS(q);
+ * q <- q + b_s res.  q: device [5][E][Np], updated in place.  work: device
+ * scratch of at least 2 * 5 * E * Np doubles, caller-owned, contents
+ * overwritten.  t is accepted for non-autonomous models (the Euler RHS does
+ * not depend on it).  Each stage is one fused launch (RHS + stage update into
+ * a second state buffer); a final copy returns the state to q. */
+dg_status dg_rk_step(dg_mesh m, const dg_params* prm, dg_precision prec, double* q, double* work,
+                     double t, double dt, hipStream_t stream);
+
+/* Pointwise stage update used by unfused stepping:
+ *   res <- a * res + dt * rhs;  q <- q + b * res   over n doubles. */
+dg_status dg_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,
+                         double* q, hipStream_t stream);
+
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

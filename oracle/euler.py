@@ -74,6 +74,34 @@ def rhs(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: float = GAMMA,
     return out
 
 
+def rhs_term_magnitude(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: float = GAMMA, elems=None):
+    """Magnitude of the terms summed into each RHS entry,
+    T_i = sum_a sum_j |D_a[i, j]| |G_{a,j}| + sum_{(f,m)} |LIFT[i, (f,m)]| |Delta_{(f,m)}|,
+    the scale of the floating-point dot-product error bound (Higham, Accuracy
+    and Stability of Numerical Algorithms, Sec. 3.1).  Same shape as rhs()."""
+    E = q.shape[1]
+    idx = np.arange(E) if elems is None else np.asarray(elems, dtype=np.int64)
+    qe = q[:, idx, :]
+    (Fx, Fy, Fz), _, _ = _fluxes(qe, gamma)
+    rx = geo["rst_x"][idx]
+    out = np.zeros_like(qe)
+    for a, D in enumerate((ops["Dr"], ops["Ds"], ops["Dt"])):
+        G = rx[None, :, a, 0, None] * Fx + rx[None, :, a, 1, None] * Fy + rx[None, :, a, 2, None] * Fz
+        out += np.abs(G) @ np.abs(D).T
+    Nfp = ops["Nfp"]
+    fm = ops["Fmask"].reshape(-1)
+    qM = qe[:, :, fm]
+    qP = q[:, conn["mapP_elem"][idx], conn["mapP_node"][idx]]
+    n = np.repeat(geo["normals"][idx], Nfp, axis=1)
+    Fs = np.repeat(geo["Fscale"][idx], Nfp, axis=1)
+    (FxM, FyM, FzM), (uM, vM, wM), cM = _fluxes(qM, gamma)
+    (FxP, FyP, FzP), (uP, vP, wP), cP = _fluxes(qP, gamma)
+    nx, ny, nz = n[..., 0], n[..., 1], n[..., 2]
+    lam = np.maximum(np.abs(uM * nx + vM * ny + wM * nz) + cM, np.abs(uP * nx + vP * ny + wP * nz) + cP)
+    delta = Fs * (0.5 * (nx * FxM + ny * FyM + nz * FzM - nx * FxP - ny * FyP - nz * FzP) - 0.5 * lam * (qM - qP))
+    return out + np.abs(delta) @ np.abs(ops["LIFT"]).T
+
+
 def max_wave_speed(q: np.ndarray, gamma: float = GAMMA) -> float:
     """max over nodes of |u| + c."""
     _, (u, v, w), c = _fluxes(q, gamma)

@@ -1,0 +1,68 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "refelem.hpp"
+
+namespace dg {
+
+// Records a failure for dg_last_error() and returns its status.
+dg_status fail(dg_status s, const std::string& msg);
+dg_status hip_fail(hipError_t e, const char* what);
+
+#define DG_HIP(call)                                     \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) return ::dg::hip_fail(_e, #call); \
+  } while (0)
+
+// Element-local contraction operator in the register layout of the FP64
+// matrix-core tiles: for k-step ks and row block rb, lane l of a wave holds
+// Op[row(rb, l)][4 ks + l / 16] where Op = [-Dr | -Ds | -Dt | LIFT] with each
+// differentiation block padded to a multiple of 4 columns.  Row blocks are
+// 16-row blocks (row 16 rb + l % 16) followed by 4-row blocks
+// (row 16 NB16 + 4 (rb - NB16) + l % 4); rows >= Np are zero.
+struct OpLayout {
+  int p, Np, Nfp;
+  int NPP;   // differentiation block width padded to a multiple of 4
+  int NB16;  // number of 16-row blocks
+  int NB4;   // number of 4-row blocks
+  int KV;    // k-steps per differentiation block
+  int KL;    // k-steps of the lift block (4 Nfp / 4)
+  int KS;    // total k-steps
+  int NRB;   // NB16 + NB4
+};
+OpLayout op_layout(int p);
+
+struct Mesh {
+  int device = 0;
+  int p = 0, Np = 0, Nfp = 0;
+  int64_t E = 0;
+  int64_t Epad = 0;  // E rounded up to a multiple of 16 (SoA stride)
+  RefElem ref;
+  OpLayout lay{};
+  std::vector<double> elem_xyz;   // host copy [E][4][3]
+  std::vector<int32_t> conn_host; // [4][Epad][2]: neighbour element, code = 6 nbr_face + perm
+  std::vector<uint8_t> nbtab;     // [4][24][Nfp]: neighbour volume node of face node m
+  // device
+  double* d_geo = nullptr;        // [9][Epad] metric terms rx ry rz sx sy sz tx ty tz
+  int2* d_conn = nullptr;         // [4][Epad]
+  double* d_op64 = nullptr;       // [KS][NRB][64]
+  int* d_fmask = nullptr;         // [4][Nfp]
+  uint8_t* d_nbtab = nullptr;     // [4][24][Nfp]
+};
+
+// kernel launchers (defined in the .hip files)
+// RHS of q; with fused_lsrk the result goes through the stage update
+// (res <- a res + dt rhs; q_out <- q + b res) instead of being stored in rhs.
+dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, double* rhs, double* res,
+                                double* q_out, double a, double b, double dt, bool fused_lsrk, hipStream_t s);
+dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,
+                             double* q, hipStream_t s);
+
+}  // namespace dg

@@ -1,0 +1,32 @@
+// Pointwise stage of the 2N-storage Runge-Kutta scheme, FP64:
+//   res <- a res + dt rhs;  q <- q + b res.
+// A stage with a = 0 does not read res (it may hold anything).
+#include "internal.hpp"
+
+namespace dg {
+namespace {
+
+__global__ __launch_bounds__(256) void lsrk_update_kernel(int64_t n, double a, double b, double dt,
+                                                          const double* __restrict__ rhs, double* __restrict__ res,
+                                                          double* __restrict__ q) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double r = (a == 0.0 ? 0.0 : a * res[i]) + dt * rhs[i];
+    res[i] = r;
+    q[i] = q[i] + b * r;
+  }
+}
+
+}  // namespace
+
+dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res, double* q,
+                             hipStream_t s) {
+  const int64_t threads = 256;
+  int64_t blocks = (n + threads - 1) / threads;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  lsrk_update_kernel<<<static_cast<unsigned>(blocks), threads, 0, s>>>(n, a, b, dt, rhs, res, q);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+}  // namespace dg

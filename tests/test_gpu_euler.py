@@ -1,0 +1,207 @@
+"""GPU parity of the HIP DG Euler path against the FP64 oracle, through the
+C ABI.  Bar (FP64, 1e-12): for every field f,
+  max|gpu - oracle| <= 1e-12 * max T_f,
+where T is the magnitude of the terms summed into each RHS entry (the scale of
+the floating-point dot-product error bound), and for every field that is not
+a near-cancellation (max|rhs_f| >= 1e-3 max T_f) also
+  max|gpu - oracle| <= 1e-12 * max|rhs_f|.
+Summation order differs between the two sides, so bit equality is not
+expected."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import euler as oe, lsrk as olsrk, mesh as om, reference_element as ore
+from paper_2512_17101_amd import dg, workload as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-12
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _case(order, dims, lengths=(10.0, 10.0, 10.0), jitter=0.05, seed=1001, pert_seed=None, state="vortex"):
+    xyz, vid = wl.kuhn_mesh(dims, lengths, jitter, seed)
+    ops = ore.operators(order)
+    geo = om.geometry(xyz)
+    conn = om.connectivity(vid, order)
+    X = om.node_coordinates(xyz, ops["rst"])
+    if state == "vortex":
+        pert = wl.density_perturbation(pert_seed) if pert_seed is not None else None
+        q = wl.vortex_state(X, pert=pert)
+    else:
+        q = wl.constant_state(X.shape[:2])
+    return dict(xyz=xyz, vid=vid, ops=ops, geo=geo, conn=conn, X=X, q=q)
+
+
+def _gpu_rhs(mesh, q_np):
+    q = torch.from_numpy(q_np).to(_dev())
+    out = torch.empty_like(q)
+    dg.rhs(mesh, q, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _assert_parity(got, ref, T, tol=TOL, label=""):
+    err = np.abs(got - ref).max(axis=(1, 2))
+    sT = T.max(axis=(1, 2))
+    sR = np.abs(ref).max(axis=(1, 2))
+    strict = sR >= 1e-3 * sT
+    print(f"{label} err/maxT {err / sT}  err/max|rhs| {err / np.maximum(sR, 1e-300)}  strict fields {strict}")
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= tol * sT)
+    assert np.all(err[strict] <= tol * sR[strict])
+
+
+def _check(c, got, elems=None, label=""):
+    ref = oe.rhs(c["ops"], c["geo"], c["conn"], c["q"], elems=elems)
+    T = oe.rhs_term_magnitude(c["ops"], c["geo"], c["conn"], c["q"], elems=elems)
+    _assert_parity(got if elems is None else got[:, elems], ref, T, label=label)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_mesh_nodes_and_face_map_match_oracle(p):
+    _dev()
+    c = _case(p, (3, 4, 5))
+    mesh = dg.Mesh(p, c["xyz"], c["vid"])
+    np.testing.assert_allclose(mesh.nodes(), c["X"], atol=1e-13)
+    ne, nn = mesh.face_map()
+    assert np.array_equal(ne, c["conn"]["mapP_elem"])
+    assert np.array_equal(nn, c["conn"]["mapP_node"])
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_rhs_parity_ragged_mesh(p):
+    # 3 x 4 x 5 cells = 360 tets: 22 full tiles of 16 plus a ragged tail of 8
+    _dev()
+    c = _case(p, (3, 4, 5), pert_seed=7)
+    mesh = dg.Mesh(p, c["xyz"], c["vid"])
+    _check(c, _gpu_rhs(mesh, c["q"]), label=f"p={p} E={mesh.E}")
+
+
+def test_rhs_parity_vortex_p2_4cubed():
+    """384 tets, p = 2, +-5 % jitter, isentropic vortex (the small workload)."""
+    _dev()
+    c = _case(2, (4, 4, 4), seed=1001)
+    mesh = dg.Mesh(2, c["xyz"], c["vid"])
+    _check(c, _gpu_rhs(mesh, c["q"]), label="vortex p2 4^3")
+
+
+def test_rhs_parity_multi_tile_p3():
+    _dev()
+    c = _case(3, (8, 8, 8), jitter=0.03, seed=5, pert_seed=2002)
+    mesh = dg.Mesh(3, c["xyz"], c["vid"])
+    _check(c, _gpu_rhs(mesh, c["q"]), label="p3 8^3")
+
+
+def test_rhs_free_stream_p3():
+    _dev()
+    c = _case(3, (4, 5, 3), state="const")
+    mesh = dg.Mesh(3, c["xyz"], c["vid"])
+    got = _gpu_rhs(mesh, c["q"])
+    S = oe.max_wave_speed(c["q"]) * np.abs(c["q"]).max() * c["geo"]["Fscale"].max()
+    assert np.abs(got).max() <= TOL * S
+
+
+def test_rhs_full_size_sampled_p3_48cubed():
+    """663,552 tets, p = 3, 3 % jitter, perturbed vortex: the full workload in
+    the launch configuration the benchmark times; the oracle evaluates a
+    sample of elements (first and last tiles, plus 4096 random ones)."""
+    dev = _dev()
+    xyz, vid = wl.kuhn_box_mesh(48, 10.0, 0.03, 1002)
+    mesh = dg.Mesh(3, xyz, vid)
+    Xg = mesh.nodes()
+    q_np = wl.vortex_state(Xg, pert=wl.density_perturbation(2002))
+    got = _gpu_rhs(mesh, q_np)
+    c = dict(ops=ore.operators(3), geo=om.geometry(xyz), conn=om.connectivity(vid, 3), q=q_np)
+    E = xyz.shape[0]
+    rng = np.random.default_rng(12)
+    idx = np.unique(np.concatenate([np.arange(16), np.arange(E - 16, E), rng.choice(E, 4096, replace=False)]))
+    _check(c, got, elems=idx, label="48^3 sampled")
+    assert np.all(np.isfinite(got))
+
+
+def test_rk_step_parity_vortex_p2_10_steps():
+    """Ten LSRK(5,4) steps at CFL 0.2 on the small workload."""
+    dev = _dev()
+    c = _case(2, (4, 4, 4), seed=1001)
+    mesh = dg.Mesh(2, c["xyz"], c["vid"])
+    dt = oe.cfl_dt(c["ops"], c["geo"], c["q"], 0.2)
+    f = lambda qq, tt: oe.rhs(c["ops"], c["geo"], c["conn"], qq)
+    qo = c["q"].copy()
+    for s in range(10):
+        qo, _ = olsrk.lsrk_step(f, qo, s * dt, dt)
+    q = torch.from_numpy(c["q"]).to(dev)
+    work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
+    for s in range(10):
+        dg.rk_step(mesh, q, work, s * dt, dt)
+    torch.cuda.synchronize()
+    got = q.cpu().numpy()
+    # momentum components are scaled by the momentum vector's magnitude (the
+    # z-momentum of the z-independent vortex stays near zero)
+    scale = np.abs(qo).max(axis=(1, 2))
+    scale[1:4] = scale[1:4].max()
+    err = np.abs(got - qo).max(axis=(1, 2)) / scale
+    print("10-step per-field rel err", err)
+    assert np.all(err <= TOL)
+
+
+def test_lsrk_update_matches_definition():
+    dev = _dev()
+    rng = np.random.default_rng(3)
+    n = 100003
+    rhs_, res, q = (rng.standard_normal(n) for _ in range(3))
+    a, b, dt = float(olsrk.A[2]), float(olsrk.B[2]), 0.0123
+    r_exp = a * res + dt * rhs_
+    q_exp = q + b * r_exp
+    t_rhs, t_res, t_q = (torch.from_numpy(x.copy()).to(dev) for x in (rhs_, res, q))
+    dg.lsrk_update(a, b, dt, t_rhs, t_res, t_q)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(t_res.cpu().numpy(), r_exp, rtol=0, atol=1e-15 * np.abs(r_exp).max())
+    np.testing.assert_allclose(t_q.cpu().numpy(), q_exp, rtol=0, atol=1e-15 * np.abs(q_exp).max())
+    # a = 0 ignores whatever res holds
+    t_res.fill_(float("nan"))
+    dg.lsrk_update(0.0, b, dt, t_rhs, t_res, t_q)
+    torch.cuda.synchronize()
+    assert torch.isfinite(t_res).all()
+
+
+def test_rhs_is_deterministic():
+    dev = _dev()
+    c = _case(3, (4, 4, 4), pert_seed=9)
+    mesh = dg.Mesh(3, c["xyz"], c["vid"])
+    q = torch.from_numpy(c["q"]).to(dev)
+    o1, o2 = torch.empty_like(q), torch.empty_like(q)
+    dg.rhs(mesh, q, o1)
+    dg.rhs(mesh, q, o2)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+
+
+def test_error_paths():
+    dev = _dev()
+    c = _case(2, (3, 3, 3))
+    mesh = dg.Mesh(2, c["xyz"], c["vid"])
+    q = torch.from_numpy(c["q"]).to(dev)
+    with pytest.raises(dg.DGError) as ei:
+        dg.rhs(mesh, q, q)
+    assert ei.value.status == 1
+    bad = c["xyz"].copy()
+    bad[4, [2, 3]] = bad[4, [3, 2]]
+    with pytest.raises(dg.DGError) as ei:
+        dg.Mesh(2, bad, c["vid"])
+    assert ei.value.status == 2
+    xyz1, vid1 = wl.kuhn_mesh((1, 1, 1), (1.0, 1.0, 1.0), 0.0, 0)
+    with pytest.raises(dg.DGError) as ei:
+        dg.Mesh(2, xyz1, vid1)  # a single periodic cube shares faces more than twice
+    assert ei.value.status == 2
+    with pytest.raises(dg.DGError) as ei:
+        dg.Mesh(5, c["xyz"], c["vid"])
+    assert ei.value.status == 1

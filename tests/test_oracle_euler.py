@@ -46,6 +46,16 @@ def test_discrete_conservation(mesh_p):
     assert np.all(np.abs(tot) <= 1e-13 * scale)
 
 
+def test_term_magnitude_bounds_rhs(mesh_p):
+    ops, geo, conn, X = mesh_p
+    q = wl.vortex_state(X, pert=wl.density_perturbation(3))
+    r = oe.rhs(ops, geo, conn, q)
+    T = oe.rhs_term_magnitude(ops, geo, conn, q)
+    assert np.all(np.abs(r) <= T * (1 + 1e-12) + 1e-300)
+    idx = np.array([0, 5, 17])
+    np.testing.assert_allclose(oe.rhs_term_magnitude(ops, geo, conn, q, elems=idx), T[:, idx], rtol=1e-13)
+
+
 def test_entropy_wave_linearity(mesh_p):
     ops, geo, conn, X = mesh_p
     vel = np.array([0.4, -0.25, 0.15])
