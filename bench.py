@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "split_bf16"])
     ap.add_argument("--cpu-sample", type=int, default=262144, help="elements in the CPU-baseline sample (0: skip)")
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="cubes per side (default: the 48^3 workload)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by element "
@@ -106,6 +108,15 @@ def main():
 
     from paper_2512_17101_amd import dg, workload as wl
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 5}), flush=True)
+        return
     p = WORKLOAD["order"]
     xyz, vid = wl.kuhn_box_mesh(args.n, 10.0, WORKLOAD["jitter"], WORKLOAD["mesh_seed"])
     mesh = dg.Mesh(p, xyz, vid, 0)
