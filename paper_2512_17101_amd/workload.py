@@ -167,3 +167,107 @@ WORKLOADS = {
     "vortex_p2_4cubed": dict(n=4, order=2, jitter=0.05, mesh_seed=1001, pert_seed=None),
     "vortex_pert_p3_48cubed": dict(n=48, order=3, jitter=0.03, mesh_seed=1002, pert_seed=2002),
 }
+
+
+# ---------------------------------------------------------------------------
+# Reacting-flow inputs: seeded synthetic species data, mechanism and fields.
+# These are input tables only (the thermodynamic and kinetic laws that use
+# them live in the library and, separately, in the oracle).
+
+R_UNIVERSAL = 8.314462618  # J / (mol K)
+N_SPECIES = 7
+N_REACTIONS = 3
+# R1: S1 + S2 -> S3 + S4 ;  R2: S3 + S2 -> S5 ;  R3: S4 + S5 -> S6 ;  S7 inert
+NU_REACTANTS = np.array([[1, 1, 0, 0, 0, 0, 0], [0, 1, 1, 0, 0, 0, 0], [0, 0, 0, 1, 1, 0, 0]], dtype=np.float64)
+NU_PRODUCTS = np.array([[0, 0, 1, 1, 0, 0, 0], [0, 0, 0, 0, 1, 0, 0], [0, 0, 0, 0, 0, 1, 0]], dtype=np.float64)
+
+
+def synthetic_thermo(seed: int = 3003):
+    """Seeded 7-species table: molar masses W [kg/mol] that balance the three
+    reactions' mass, and single-range polynomial coefficients a[k] = (a1..a6)
+    with cp_k / R_k = a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4 in [2.5, 10] and
+    increasing on [200, 4000] K, and a6 [K] set from seeded molar formation
+    enthalpies at 298.15 K so that every reaction is exothermic."""
+    rng = np.random.default_rng(seed)
+    W = np.zeros(N_SPECIES)
+    W[0] = rng.uniform(0.010, 0.020)
+    W[1] = rng.uniform(0.025, 0.035)
+    W[2] = rng.uniform(0.010, W[0] + W[1] - 0.008)
+    W[3] = W[0] + W[1] - W[2]
+    W[4] = W[2] + W[1]
+    W[5] = W[3] + W[4]
+    W[6] = rng.uniform(0.026, 0.030)
+    a = np.zeros((N_SPECIES, 6))
+    for k in range(N_SPECIES):
+        c = np.array([rng.uniform(2.5, 3.5), rng.uniform(0.5, 2.5), rng.uniform(0.0, 2.0),
+                      rng.uniform(0.0, 1.0), rng.uniform(0.0, 0.5)])
+        # cp/R = sum_m c_m s^m with s = (T - 200) / 3800: expand in powers of T
+        poly = np.zeros(5)
+        for m in range(5):
+            # (T - 200)^m / 3800^m = sum_j binom(m, j) T^j (-200)^(m-j) / 3800^m
+            for j in range(m + 1):
+                poly[j] += c[m] * math.comb(m, j) * (-200.0) ** (m - j) / 3800.0 ** m
+        a[k, :5] = poly
+    h_form = np.array([50e3, 0.0, -100e3, -150e3, -250e3, -500e3, 0.0]) * rng.uniform(0.9, 1.1, N_SPECIES)
+    T0 = 298.15
+    for k in range(N_SPECIES):
+        p5 = a[k, 0] * T0 + a[k, 1] * T0 ** 2 / 2 + a[k, 2] * T0 ** 3 / 3 + a[k, 3] * T0 ** 4 / 4 + a[k, 4] * T0 ** 5 / 5
+        a[k, 5] = h_form[k] / R_UNIVERSAL - p5
+    return {"W": W, "a": a}
+
+
+def synthetic_mechanism(seed: int = 3004):
+    """Seeded irreversible 3-step mechanism: pre-exponential factors A
+    log-uniform in [1e8, 1e12] (SI, mol-m^3-s), activation energies Ea uniform
+    in [1e4, 2e5] J/mol, reactant / product stoichiometry as above."""
+    rng = np.random.default_rng(seed)
+    A = 10.0 ** rng.uniform(8.0, 12.0, N_REACTIONS)
+    Ea = rng.uniform(1e4, 2e5, N_REACTIONS)
+    return {"A": A, "Ea": Ea, "nu_r": NU_REACTANTS.copy(), "nu_p": NU_PRODUCTS.copy()}
+
+
+def reacting_fields(xyz, seed: int = 3005, L: float = 0.01, n_cells: int = 32, n_spheres: int = 4):
+    """Seeded smooth front indicator S in [0, 1] (tanh fronts of seeded
+    periodic spheres, width 4 h) and a smooth periodic velocity field of
+    amplitude 1 m/s at node coordinates.  Returns (S, u, v, w)."""
+    rng = np.random.default_rng(seed)
+    h = L / n_cells
+    centers = rng.uniform(0.0, L, (n_spheres, 3))
+    radii = rng.uniform(0.15 * L, 0.3 * L, n_spheres)
+    S = np.zeros(xyz.shape[:-1])
+    for c, r in zip(centers, radii):
+        d = xyz - c
+        d = (d + 0.5 * L) % L - 0.5 * L
+        dist = np.sqrt((d * d).sum(-1))
+        S = np.maximum(S, 0.5 * (1.0 - np.tanh((dist - r) / (4.0 * h))))
+    k = rng.integers(1, 3, (3, 3))
+    ph = rng.uniform(0, 2 * math.pi, (3,))
+    u = np.sin(2 * math.pi * (xyz @ k[0].astype(float)) / L + ph[0])
+    v = np.sin(2 * math.pi * (xyz @ k[1].astype(float)) / L + ph[1])
+    w = np.sin(2 * math.pi * (xyz @ k[2].astype(float)) / L + ph[2])
+    return S, u, v, w
+
+
+# Endpoints of the reacting state: a cold fuel/oxidizer/inert mixture and a
+# hot product mixture.  The internal energies and densities are those of the
+# default seeded species table at about 300 K and 2200 K and 1 atm; the state
+# blends them along the front indicator, so each solver's own Newton solve
+# yields a temperature field of roughly 300..2200 K.
+Y_COLD = np.array([0.06, 0.22, 0.0, 0.0, 0.0, 0.0, 0.72])
+Y_HOT = np.array([0.005, 0.04, 0.03, 0.02, 0.06, 0.125, 0.72])
+E_COLD, E_HOT = 1.7934e5, -1.9697e5      # J/kg
+RHO_COLD, RHO_HOT = 1.0926, 0.17571      # kg/m^3
+
+
+def reacting_state(xyz, seed: int = 3005, L: float = 0.01, n_cells: int = 32):
+    """Conserved reacting state q[12][...] = (rho, rho u, rho v, rho w, E,
+    rho Y_1 .. rho Y_7): density, internal energy and mass fractions blended
+    between the cold and hot endpoints along a seeded front, plus a seeded
+    velocity field; E = rho (e + |u|^2 / 2)."""
+    S, u, v, w = reacting_fields(xyz, seed, L, n_cells)
+    rho = RHO_COLD * (1.0 - S) + RHO_HOT * S
+    e = E_COLD * (1.0 - S) + E_HOT * S
+    Y = (1.0 - S)[None] * Y_COLD.reshape((-1,) + (1,) * S.ndim) + S[None] * Y_HOT.reshape((-1,) + (1,) * S.ndim)
+    E = rho * (e + 0.5 * (u * u + v * v + w * w))
+    q = np.concatenate([np.stack([rho, rho * u, rho * v, rho * w, E]), rho[None] * Y], axis=0)
+    return np.ascontiguousarray(q)
