@@ -9,7 +9,9 @@ periodic isentropic-vortex Euler benchmark (Sec. 5.2).
 A step is one evaluation of the full right-hand side (volume divergence, face
 gather with the Lax-Friedrichs flux, lift and inverse mass) over the whole
 mesh; the state is resident in HBM before timing starts.  Throughput is
-GDOF.fields/s = E * Np * nf * steps / time / 1e9.
+GDOF.fields/s = E * Np * nf * steps / time / 1e9.  The reported value is the
+FP64 form; the FP32 and split-BF16 contraction forms are timed the same way
+and listed under "variants" with their per-field errors against the oracle.
 
 Prints ONE JSON line.  Also reports the roofline of the RHS kernel (its
 launch duration measured with HIP events on the stream it runs on) and the
@@ -69,7 +71,8 @@ def stored_traffic():
 
 def cpu_baseline(xyz, vid, q_np, p, sample_elems):
     """Oracle RHS timed on a contiguous sample of elements (BLAS limited to one
-    thread, so one core does the work)."""
+    thread, so one core does the work).  Returns (record, element ids, oracle
+    RHS on them)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import euler as oe, mesh as om, reference_element as ore
@@ -82,10 +85,58 @@ def cpu_baseline(xyz, vid, q_np, p, sample_elems):
         t0 = time.perf_counter()
         oe.rhs(ops, geo, conn, q_np, elems=idx)
         t = time.perf_counter() - t0
+        ref = oe.rhs(ops, geo, conn, q_np, elems=idx)
     Np = ops["Np"]
-    return {"value": len(idx) * Np * NF / t / 1e9, "unit": "GDOF·fields/s", "cores": 1, "kind": "oracle",
-            "sample": f"one RHS over elements 0..{len(idx) - 1} of the {xyz.shape[0]}-tet mesh "
-                      f"({t:.1f} s, NumPy FP64, 1 thread)"}
+    rec = {"value": len(idx) * Np * NF / t / 1e9, "unit": "GDOF·fields/s", "cores": 1, "kind": "oracle",
+           "sample": f"one RHS over elements 0..{len(idx) - 1} of the {xyz.shape[0]}-tet mesh "
+                     f"({t:.1f} s, NumPy FP64, 1 thread)"}
+    return rec, idx, ref
+
+
+def field_errors(got, ref):
+    """Per-field relative L2 and Linf errors (momentum components scaled by the
+    momentum vector's magnitude)."""
+    d = got - ref
+    l2 = np.sqrt((d ** 2).sum(axis=(1, 2)))
+    n2 = np.sqrt((ref ** 2).sum(axis=(1, 2)))
+    li = np.abs(d).max(axis=(1, 2))
+    ni = np.abs(ref).max(axis=(1, 2))
+    n2[1:4] = n2[1:4].max()
+    ni[1:4] = ni[1:4].max()
+    names = ("rho", "rho_u", "rho_v", "rho_w", "E")
+    return {nm: {"l2": float(l2[f] / n2[f]), "linf": float(li[f] / ni[f])} for f, nm in enumerate(names)}
+
+
+def time_rhs(dg, mesh, q, out, precision, steps, warmup, stream):
+    """Average duration of one dg_rhs launch, HIP events on its stream."""
+    import torch
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            dg.rhs(mesh, q, out, precision, stream=stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            dg.rhs(mesh, q, out, precision, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_rk_step(dg, mesh, q, work, dt, precision, steps, stream):
+    import torch
+    with torch.cuda.stream(stream):
+        dg.rk_step(mesh, q, work, 0.0, dt, precision, stream=stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            dg.rk_step(mesh, q, work, 0.0, dt, precision, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+    return e0.elapsed_time(e1) / steps
 
 
 def main():
@@ -93,7 +144,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "split_bf16"])
+    ap.add_argument("--precision", default="all", choices=["all", "fp64", "fp32", "split_bf16"],
+                    help="contraction precision; 'all' times FP64 (the reported value) then FP32 and split BF16")
+    ap.add_argument("--no-rk", action="store_true", help="skip the LSRK step timing")
     ap.add_argument("--cpu-sample", type=int, default=262144, help="elements in the CPU-baseline sample (0: skip)")
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="cubes per side (default: the 48^3 workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -123,42 +176,62 @@ def main():
     X = mesh.nodes()
     q_np = wl.vortex_state(X, pert=wl.density_perturbation(WORKLOAD["pert_seed"]))
     q = torch.from_numpy(q_np).to(dev)
-    out = torch.empty_like(q)
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            dg.rhs(mesh, q, out, args.precision, stream=stream)
-        stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            dg.rhs(mesh, q, out, args.precision, stream=stream)
-        e1.record(stream)
-        stream.synchronize()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps  # one launch per step: this is the kernel's average duration
     E, Np = mesh.E, mesh.Np
-    value = E * Np * NF / (ms * 1e-3) / 1e9
+    modes = ["fp64", "fp32", "split_bf16"] if args.precision == "all" else [args.precision]
+    outs, ms = {}, {}
+    for mode in modes:
+        outs[mode] = torch.empty_like(q)
+        ms[mode] = time_rhs(dg, mesh, q, outs[mode], mode, args.steps, args.warmup, stream)
+    torch.cuda.synchronize()
+    head = modes[0]
+    value = E * Np * NF / (ms[head] * 1e-3) / 1e9
     flops, bytes_ = algorithmic_counts(p)
-    achieved_tf = flops * E / (ms * 1e-3) / 1e12
-    achieved_gbs = bytes_ * E / (ms * 1e-3) / 1e9
-    traffic = stored_traffic()
+    achieved_tf = flops * E / (ms[head] * 1e-3) / 1e12
+    achieved_gbs = bytes_ * E / (ms[head] * 1e-3) / 1e9
+    traffic = stored_traffic() if head == "fp64" else None
+    kernel = f"rhs_euler_fp64_kernel<{p}>" if head == "fp64" else f"rhs_euler_lowp_kernel<{p}>"
     roofline = {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                "kernel": f"rhs_euler_fp64_kernel<{p}>", "flops_per_elem": flops, "bytes_per_elem": bytes_,
+                "kernel": kernel, "flops_per_elem": flops, "bytes_per_elem": bytes_,
                 "hbm_view": {"achieved": round(achieved_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(achieved_gbs / PEAK_HBM_GBS, 4)}}
     rec = {"metric": METRIC, "value": round(value, 3), "unit": "GDOF·fields/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms[head], 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3-f32acc"}[head], "data": "synthetic",
            "config": {"workload": WORKLOAD["name"] if args.n == WORKLOAD["n"] else f"euler_vortex_pert_p3_{args.n}cubed",
                       "elements": E, "order": p, "nodes_per_element": Np, "fields": NF,
-                      "contraction_precision": args.precision},
+                      "contraction_precision": head},
            "roofline": roofline}
+    variants = {}
+    for mode in modes[1:]:
+        gbs = bytes_ * E / (ms[mode] * 1e-3) / 1e9
+        variants[mode] = {"value": round(E * Np * NF / (ms[mode] * 1e-3) / 1e9, 3), "ms_per_step": round(ms[mode], 5),
+                          "speedup_vs_fp64": round(ms[head] / ms[mode], 3),
+                          "hbm_view": {"achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                       "frac": round(gbs / PEAK_HBM_GBS, 4)}}
+    if not args.no_rk:
+        work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
+        qs = q.clone()
+        for mode in modes:
+            t_rk = time_rk_step(dg, mesh, qs, work, 1e-4, mode, max(2, args.steps // 10), stream)
+            (rec if mode == head else variants[mode])["lsrk_step_ms"] = round(t_rk, 4)
+        del work, qs
     if args.cpu_sample > 0:
-        rec["cpu_baseline"] = cpu_baseline(xyz, vid, q_np, p, args.cpu_sample)
+        cpu, idx, ref = cpu_baseline(xyz, vid, q_np, p, args.cpu_sample)
+        rec["cpu_baseline"] = cpu
+        idx_t = torch.from_numpy(idx).to(dev)
+        for mode in modes:
+            got = outs[mode].index_select(1, idx_t).cpu().numpy()
+            errs = field_errors(got, ref)
+            if mode == head:
+                rec["error_vs_oracle"] = errs
+            else:
+                variants[mode]["error_vs_oracle"] = errs
+    if variants:
+        rec["variants"] = variants
     print(json.dumps(rec), flush=True)
 
 

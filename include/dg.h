@@ -26,7 +26,7 @@
  *    aligned at least (256-byte recommended); the library never frees them and
  *    keeps no pointer past return.  Compute calls are asynchronous on the given
  *    HIP stream (0 = the null stream); argument checks are synchronous.
- *  - Handles (dg_mesh) own their device copies; dg_mesh_destroy frees them.
+ *  - Handles (dg_mesh, dg_thermo, dg_mech) own their tables; *_destroy frees them.
  *    A handle is immutable after creation, so calls on different streams may
  *    share it.
  */
@@ -101,8 +101,11 @@ dg_status dg_mesh_destroy(dg_mesh m);
  *         + LIFT * ( Fscale * [ 1/2 n.(F(q-) - F(q+)) - 1/2 lam (q- - q+) ] )
  * with the local Lax-Friedrichs speed lam = max(|u-.n| + c-, |u+.n| + c+) at
  * every face node.  q, rhs: device [5][E][Np] FP64 (must not alias).
- * prec selects the contraction precision (DG_FP64 only in this build:
- * others return DG_ERR_UNSUPPORTED).  Asynchronous on `stream`. */
+ * prec selects the contraction precision: DG_FP64; DG_FP32 (operator and
+ * operands rounded to FP32, FP32 accumulation); DG_SPLIT_BF16 (x = hi + lo
+ * with hi = bf16(fp32(x)), lo = bf16(fp32(x) - hi), Op X ~ Op_hi X_hi +
+ * Op_hi X_lo + Op_lo X_hi accumulated in FP32).  Fluxes, jumps and the
+ * result are FP64 in every mode.  Asynchronous on `stream`. */
 dg_status dg_rhs(dg_mesh m, const dg_params* prm, dg_precision prec, const double* q, double* rhs,
                  hipStream_t stream);
 
@@ -120,6 +123,91 @@ dg_status dg_rk_step(dg_mesh m, const dg_params* prm, dg_precision prec, double*
  *   res <- a * res + dt * rhs;  q <- q + b * res   over n doubles. */
 dg_status dg_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,
                          double* q, hipStream_t stream);
+
+/* ---- reacting flow: species thermodynamics, temperature, sources -------- */
+/* State of a reacting mixture: q[5 + ns][n] FP64 field-major (n points),
+ * fields (rho, rho u, rho v, rho w, E_total, rho Y_1 .. rho Y_ns), SI units. */
+
+typedef struct dg_thermo_s* dg_thermo;
+typedef struct dg_mech_s* dg_mech;
+
+/* Species table for temperature-dependent thermodynamics (the paper's
+ * multispecies reacting flow, Sec. 5; one-range polynomial reading):
+ * R_k = R_u / W_k, cp_k/R_k = a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4,
+ * h_k/R_k = a1 T + a2 T^2/2 + a3 T^3/3 + a4 T^4/4 + a5 T^5/5 + a6, e_k = h_k - R_k T.
+ *   W       host [ns]     molar masses, kg/mol, > 0
+ *   coeffs  host [ns][6]  (a1 .. a6), a6 in K
+ * ns in 1..8.  The handle keeps a host copy (passed to kernels by value). */
+dg_status dg_thermo_create(int n_species, const double* W, const double* coeffs, int device, dg_thermo* out);
+dg_status dg_thermo_destroy(dg_thermo th);
+
+/* Irreversible Arrhenius mechanism over the species of `th`:
+ * k_j = A_j exp(-Ea_j / (R_u T)), r_j = k_j prod_k C_k^{nu'_kj}, C_k = rho Y_k / W_k,
+ * omega_k = W_k sum_j (nu''_kj - nu'_kj) r_j  [kg / (m^3 s)].
+ *   A, Ea       host [nr]      (SI: mol, m^3, s; J/mol), A >= 0
+ *   nu_r, nu_p  host [nr][ns]  reactant / product coefficients, integers 0..3
+ * nr in 1..8. */
+dg_status dg_mech_create(dg_thermo th, int n_reactions, const double* A, const double* Ea, const int32_t* nu_r,
+                         const int32_t* nu_p, dg_mech* out);
+dg_status dg_mech_destroy(dg_mech m);
+
+/* Temperature from the conserved state by Newton's method on
+ * e(T; Y) = E/rho - |m|^2/(2 rho^2):  T <- T - (e(T) - e) / cv(T),
+ * cv = sum Y_k (cp_k - R_k), iterates clamped to [100, 6000] K, stopping when
+ * |T_{n+1} - T_n| < tol.  q: device [5+ns][n]; T_guess: device [n] initial
+ * iterates, or NULL to start every point at T_default; T_out: device [n];
+ * iters: device int32 [n], the step count, or -1 where max_iter steps did not
+ * converge (T_out then holds the last iterate).  Asynchronous on `stream`. */
+dg_status dg_temperature(dg_thermo th, int64_t n, const double* q, const double* T_guess, double T_default,
+                         double* T_out, int32_t* iters, double tol, int max_iter, hipStream_t stream);
+
+/* Species mass sources omega: device [ns][n] from q (device [5+ns][n]) and
+ * T (device [n]).  Asynchronous on `stream`. */
+dg_status dg_sources(dg_mech mech, int64_t n, const double* q, const double* T, double* omega, hipStream_t stream);
+
+/* ---- learned temperature guess ------------------------------------------ */
+/* Multilayer perceptron x -> T0 with widths 9 -> 64 -> 64 -> 64 -> 1 and tanh
+ * (9,025 parameters), x = standardised (log rho, e, Y_1 .. Y_7).  BF16 operands
+ * on the matrix cores with FP32 accumulation; bias and tanh in FP32,
+ * activations rounded to BF16; FP32 master weights and Adam moments.
+ * Parameter vector (host FP32 [9025]): W1[64][9], b1[64], W2[64][64], b2[64],
+ * W3[64][64], b3[64], W4[1][64], b4[1].  Training data are columns of a
+ * reacting state q (device [12][ld]) selected by idx (device int64 [batch])
+ * with targets T (device [ld]).  A handle's scratch and Adam state are shared
+ * by every call on it: calls on one handle must not overlap. */
+typedef struct dg_mlp_s* dg_mlp;
+
+/* Glorot-uniform weights (seeded), zero biases, identity normalisation. */
+dg_status dg_mlp_create(int device, uint64_t seed, dg_mlp* out);
+dg_status dg_mlp_destroy(dg_mlp m);
+/* Replace / read the FP32 master parameters (set also clears Adam state). */
+dg_status dg_mlp_set_params(dg_mlp m, const float* params);
+dg_status dg_mlp_get_params(dg_mlp m, float* params);
+/* Feature means / standard deviations (host [9]) and target mean / std. */
+dg_status dg_mlp_set_normalization(dg_mlp m, const double* feat_mean, const double* feat_std, double T_mean,
+                                   double T_std);
+dg_status dg_mlp_get_normalization(dg_mlp m, double* feat_mean, double* feat_std, double* T_mean, double* T_std);
+/* Normalisation fitted on the samples idx[0..n) (synchronous); a feature whose
+ * standard deviation is below 1e-6 max(|mean|, 1) is centred, not scaled. */
+dg_status dg_mlp_fit_normalization(dg_mlp m, int64_t n, int64_t ld, const double* q, const int64_t* idx,
+                                   const double* T);
+/* MSE loss mean((out - (T - T_mean)/T_std)^2) over the batch and its gradient
+ * (device FP32 [9025] in parameter order); either output may be NULL. */
+dg_status dg_mlp_loss_grad(dg_mlp m, int64_t batch, int64_t ld, const double* q, const int64_t* idx,
+                           const double* T, float* grad, float* loss, hipStream_t stream);
+/* One Adam step (betas 0.9 / 0.999, eps 1e-8, bias-corrected) on that gradient. */
+dg_status dg_mlp_train_step(dg_mlp m, int64_t batch, int64_t ld, const double* q, const int64_t* idx,
+                            const double* T, float lr, float* loss, hipStream_t stream);
+/* Predicted temperature (de-standardised, unclamped) of columns 0..n of q. */
+dg_status dg_mlp_predict(dg_mlp m, int64_t n, int64_t ld, const double* q, double* T_pred, hipStream_t stream);
+/* dg_temperature started from the clamped prediction: at most
+ * learned_max_iter Newton steps, then, where not converged, a restart from
+ * T_default with max_iter steps (counted in *fallback_count, device int32,
+ * may be NULL).  iters = total steps, -1 if the restart fails too.  The
+ * answer is the same converged root the plain solve finds.  ns must be 7. */
+dg_status dg_temperature_learned(dg_thermo th, dg_mlp m, int64_t n, const double* q, double T_default,
+                                 double* T_out, int32_t* iters, double tol, int max_iter, int learned_max_iter,
+                                 int32_t* fallback_count, hipStream_t stream);
 
 const char* dg_last_error(void);
 

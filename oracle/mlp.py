@@ -119,6 +119,16 @@ class Adam:
         return new
 
 
+def normalization(F, T):
+    """Feature means / standard deviations and target mean / std of a
+    training set; a (numerically) constant feature, std < 1e-6 max(|mean|, 1),
+    is centred but not scaled (std := 1)."""
+    mean = F.mean(axis=0)
+    std = F.std(axis=0)
+    std = np.where(std >= 1e-6 * np.maximum(np.abs(mean), 1.0), std, 1.0)
+    return mean, std, float(np.mean(T)), float(np.std(T))
+
+
 def features(q):
     """Raw features (log rho, e, Y_1 .. Y_7) [n, 9] of a reacting state q[12][...]."""
     rho = q[0].ravel()

@@ -42,7 +42,6 @@ dg_status check_params(const char* who, const dg_params* prm, dg_precision prec)
   if (!(prm->gamma > 1.0) || !std::isfinite(prm->gamma)) return fail(DG_ERR_ARG, std::string(who) + ": gamma must be > 1");
   if (prec != DG_FP64 && prec != DG_FP32 && prec != DG_SPLIT_BF16)
     return fail(DG_ERR_ARG, std::string(who) + ": unknown precision");
-  if (prec != DG_FP64) return fail(DG_ERR_UNSUPPORTED, std::string(who) + ": only DG_FP64 contractions in this build");
   return DG_OK;
 }
 
@@ -85,7 +84,8 @@ extern "C" dg_status dg_rhs(dg_mesh h, const dg_params* prm, dg_precision prec, 
   if (q == rhs || (rhs < q + n && q < rhs + n)) return fail(DG_ERR_ARG, "dg_rhs: q and rhs overlap");
   DeviceGuard g(m.device);
   if (!g.ok) return fail(DG_ERR_HIP, "dg_rhs: hipSetDevice failed");
-  return launch_rhs_euler_fp64(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+  if (prec == DG_FP64) return launch_rhs_euler_fp64(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+  return launch_rhs_euler_lowp(m, prec, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
 }
 
 extern "C" dg_status dg_rk_step(dg_mesh h, const dg_params* prm, dg_precision prec, double* q, double* work,
@@ -106,7 +106,9 @@ extern "C" dg_status dg_rk_step(dg_mesh h, const dg_params* prm, dg_precision pr
   for (int s = 0; s < 5; ++s) {
     const double* qin = buf[s & 1];
     double* qout = buf[(s + 1) & 1];
-    st = launch_rhs_euler_fp64(m, prm->gamma, qin, nullptr, res, qout, kRkA[s], kRkB[s], dt, true, stream);
+    st = prec == DG_FP64
+             ? launch_rhs_euler_fp64(m, prm->gamma, qin, nullptr, res, qout, kRkA[s], kRkB[s], dt, true, stream)
+             : launch_rhs_euler_lowp(m, prec, prm->gamma, qin, nullptr, res, qout, kRkA[s], kRkB[s], dt, true, stream);
     if (st != DG_OK) return st;
   }
   // five stages leave the state in the second buffer

@@ -1,0 +1,91 @@
+// Pointwise FP64 pieces of the Euler right-hand side shared by the element
+// kernels of every contraction precision.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dg {
+
+// Reciprocal and square root from the hardware approximations, refined by
+// Newton steps (each squares the relative error; two reach the last bit of a
+// double from the hardware's initial accuracy).
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double sqrt_pos(double a) {  // a > 0
+  double y = __builtin_amdgcn_rsq(a);
+  y = y * fma(-0.5 * a * y, y, 1.5);
+  y = y * fma(-0.5 * a * y, y, 1.5);
+  return a * y;
+}
+
+// Contravariant fluxes G_a = sum_d (da/dx_d) F_d(q) of one node for
+// a = r, s, t; gm = (grad r, grad s, grad t).  With u = m / rho,
+// p = (gamma - 1)(E - m.u / 2) and U_a = grad a . u:
+//   G_a = (rho U_a, m U_a + p grad a, (E + p) U_a).
+__device__ inline void contravariant_flux(const double qq[5], const double gm[9], double gm1, double G[3][5]) {
+  const double ir = recip(qq[0]);
+  const double u = qq[1] * ir, v = qq[2] * ir, w = qq[3] * ir;
+  const double p = gm1 * (qq[4] - 0.5 * (qq[1] * u + qq[2] * v + qq[3] * w));
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double U = gm[3 * r] * u + gm[3 * r + 1] * v + gm[3 * r + 2] * w;
+    G[r][0] = qq[0] * U;
+    G[r][1] = qq[1] * U + p * gm[3 * r];
+    G[r][2] = qq[2] * U + p * gm[3 * r + 1];
+    G[r][3] = qq[3] * U + p * gm[3 * r + 2];
+    G[r][4] = (qq[4] + p) * U;
+  }
+}
+
+// Face normal scaled by Fscale = sJ / J, from the metric: f0 {t=-1}: -grad t,
+// f1 {s=-1}: -grad s, f2 {r+s+t=-1}: grad r + grad s + grad t, f3 {r=-1}: -grad r.
+__device__ inline void scaled_normal(int face, const double gm[9], double& Nx, double& Ny, double& Nz) {
+  if (face == 0) { Nx = -gm[6]; Ny = -gm[7]; Nz = -gm[8]; }
+  else if (face == 1) { Nx = -gm[3]; Ny = -gm[4]; Nz = -gm[5]; }
+  else if (face == 2) { Nx = gm[0] + gm[3] + gm[6]; Ny = gm[1] + gm[4] + gm[7]; Nz = gm[2] + gm[5] + gm[8]; }
+  else { Nx = -gm[0]; Ny = -gm[1]; Nz = -gm[2]; }
+}
+
+// Scaled local Lax-Friedrichs jump at a face node, N = Fscale n, U_n = N . u:
+//   D = 1/2 (N.F(q-) - N.F(q+)) - 1/2 max(|U_n-| + c- |N|, |U_n+| + c+ |N|) (q- - q+).
+__device__ inline void lf_jump(const double qm[5], const double qp[5], double Nx, double Ny, double Nz,
+                               double gamma, double D[5]) {
+  const double gm1 = gamma - 1.0;
+  const double Fs = sqrt_pos(Nx * Nx + Ny * Ny + Nz * Nz);
+  const double irm = recip(qm[0]), irp = recip(qp[0]);
+  const double um = qm[1] * irm, vm = qm[2] * irm, wm = qm[3] * irm;
+  const double up = qp[1] * irp, vp = qp[2] * irp, wp = qp[3] * irp;
+  const double pm = gm1 * (qm[4] - 0.5 * (qm[1] * um + qm[2] * vm + qm[3] * wm));
+  const double pp = gm1 * (qp[4] - 0.5 * (qp[1] * up + qp[2] * vp + qp[3] * wp));
+  const double Unm = Nx * um + Ny * vm + Nz * wm;
+  const double Unp = Nx * up + Ny * vp + Nz * wp;
+  const double cm = sqrt_pos(gamma * pm * irm), cp = sqrt_pos(gamma * pp * irp);
+  const double lamFs = fmax(fabs(Unm) + cm * Fs, fabs(Unp) + cp * Fs);
+  D[0] = 0.5 * (qm[0] * Unm - qp[0] * Unp) - 0.5 * lamFs * (qm[0] - qp[0]);
+  D[1] = 0.5 * (qm[1] * Unm + pm * Nx - qp[1] * Unp - pp * Nx) - 0.5 * lamFs * (qm[1] - qp[1]);
+  D[2] = 0.5 * (qm[2] * Unm + pm * Ny - qp[2] * Unp - pp * Ny) - 0.5 * lamFs * (qm[2] - qp[2]);
+  D[3] = 0.5 * (qm[3] * Unm + pm * Nz - qp[3] * Unp - pp * Nz) - 0.5 * lamFs * (qm[3] - qp[3]);
+  D[4] = 0.5 * ((qm[4] + pm) * Unm - (qp[4] + pp) * Unp) - 0.5 * lamFs * (qm[4] - qp[4]);
+}
+
+// Output of one RHS entry: stored as is, or pushed through the 2N-storage
+// Runge-Kutta stage  res <- a res + dt rhs;  q_out <- q + b res.
+template <bool FUSED>
+__device__ inline void emit(int64_t idx, double val, double* __restrict__ rhs, double* __restrict__ res,
+                            double* __restrict__ qout, const double* __restrict__ q, double a, double b, double dt) {
+  if (!FUSED) {
+    rhs[idx] = val;
+  } else {
+    const double r = (a == 0.0 ? 0.0 : a * res[idx]) + dt * val;
+    res[idx] = r;
+    qout[idx] = q[idx] + b * r;
+  }
+}
+
+}  // namespace dg

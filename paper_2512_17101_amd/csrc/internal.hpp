@@ -39,6 +39,19 @@ struct OpLayout {
 };
 OpLayout op_layout(int p);
 
+// Layout of the reduced-precision operator tables.
+//  FP32:  op32[KS32][NR][64], lane l holding Op[16 rb + l % 16][4 ks + l / 16]
+//         (same K order as the FP64 table), 16-row blocks, rows >= Np zero.
+//  BF16:  opbf[VKS + FKS][NR][2 (hi, lo)][64][8]: lane l = i + 16 g holds
+//         8 consecutive K slots t = 8 k .. 8 k + 7 of lane group g, where the
+//         volume slots t = 3 s + a map to column a NPP + 4 s + g and the
+//         face slots t map to column 3 NPP + 4 t + g; unused slots are zero.
+//         x = fp32(Op), hi = bf16(x), lo = bf16(x - hi), round to nearest even.
+struct LowpLayout {
+  int Np, Nfp, NPP, KV, KL, NR, KS32, VKS, FKS;
+};
+LowpLayout lowp_layout(int p);
+
 struct Mesh {
   int device = 0;
   int p = 0, Np = 0, Nfp = 0;
@@ -53,6 +66,8 @@ struct Mesh {
   double* d_geo = nullptr;        // [9][Epad] metric terms rx ry rz sx sy sz tx ty tz
   int2* d_conn = nullptr;         // [4][Epad]
   double* d_op64 = nullptr;       // [KS][NRB][64]
+  float* d_op32 = nullptr;        // FP32 table (LowpLayout)
+  uint16_t* d_opbf = nullptr;     // BF16 hi/lo table (LowpLayout)
   int* d_fmask = nullptr;         // [4][Nfp]
   uint8_t* d_nbtab = nullptr;     // [4][24][Nfp]
 };
@@ -62,6 +77,10 @@ struct Mesh {
 // (res <- a res + dt rhs; q_out <- q + b res) instead of being stored in rhs.
 dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, double* rhs, double* res,
                                 double* q_out, double a, double b, double dt, bool fused_lsrk, hipStream_t s);
+// Same, with the contraction in FP32 or split BF16.
+dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, const double* q, double* rhs,
+                                double* res, double* q_out, double a, double b, double dt, bool fused_lsrk,
+                                hipStream_t s);
 dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,
                              double* q, hipStream_t s);
 

@@ -77,6 +77,63 @@ void build_op64(const RefElem& R, const OpLayout& L, std::vector<double>& A) {
       }
 }
 
+// round-to-nearest-even FP32 -> BF16 bit pattern (finite inputs)
+uint16_t bf16_bits(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return static_cast<uint16_t>(b >> 16);
+}
+float bf16_value(uint16_t h) {
+  const uint32_t b = static_cast<uint32_t>(h) << 16;
+  float x;
+  std::memcpy(&x, &b, 4);
+  return x;
+}
+
+// Op[i][col] of [-Dr | -Ds | -Dt | LIFT] with each D block padded to NPP columns
+double op_entry(const RefElem& R, int NPP, int i, int col) {
+  if (i >= R.Np) return 0.0;
+  if (col < 3 * NPP) {
+    const int a = col / NPP, j = col % NPP;
+    if (j >= R.Np) return 0.0;
+    const std::vector<double>& D = a == 0 ? R.Dr : a == 1 ? R.Ds : R.Dt;
+    return -D[i * R.Np + j];
+  }
+  return R.LIFT[i * 4 * R.Nfp + (col - 3 * NPP)];
+}
+
+void build_lowp_tables(const RefElem& R, std::vector<float>& op32, std::vector<uint16_t>& opbf) {
+  const LowpLayout L = lowp_layout(R.p);
+  op32.assign(static_cast<size_t>(L.KS32) * L.NR * 64, 0.f);
+  for (int ks = 0; ks < L.KS32; ++ks)
+    for (int rb = 0; rb < L.NR; ++rb)
+      for (int l = 0; l < 64; ++l)
+        op32[(static_cast<size_t>(ks) * L.NR + rb) * 64 + l] =
+            static_cast<float>(op_entry(R, L.NPP, 16 * rb + l % 16, 4 * ks + l / 16));
+  opbf.assign(static_cast<size_t>(L.VKS + L.FKS) * L.NR * 2 * 64 * 8, 0);
+  for (int k = 0; k < L.VKS + L.FKS; ++k)
+    for (int rb = 0; rb < L.NR; ++rb)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          const int i = 16 * rb + l % 16, g = l / 16;
+          int col = -1;
+          if (k < L.VKS) {
+            const int t = 8 * k + e;
+            if (t < 3 * L.KV) col = (t % 3) * L.NPP + 4 * (t / 3) + g;
+          } else {
+            const int t = 8 * (k - L.VKS) + e;
+            if (t < L.KL) col = 3 * L.NPP + 4 * t + g;
+          }
+          const float x = static_cast<float>(col < 0 ? 0.0 : op_entry(R, L.NPP, i, col));
+          const uint16_t hi = bf16_bits(x);
+          const uint16_t lo = bf16_bits(x - bf16_value(hi));
+          const size_t base = ((static_cast<size_t>(k) * L.NR + rb) * 2) * 64 * 8;
+          opbf[base + (0 * 64 + l) * 8 + e] = hi;
+          opbf[base + (1 * 64 + l) * 8 + e] = lo;
+        }
+}
+
 struct FaceRec {
   int64_t a, b, c;  // sorted vertex ids
   int64_t id;       // 4 * element + face
@@ -199,6 +256,9 @@ extern "C" dg_status dg_mesh_create(int order, int64_t n_elem, const double* ele
   if (!build_nbtab(m->ref, m->nbtab)) return cleanup(fail(DG_ERR_MESH, "dg_mesh_create: face-node table failed"));
   std::vector<double> op64;
   build_op64(m->ref, m->lay, op64);
+  std::vector<float> op32;
+  std::vector<uint16_t> opbf;
+  build_lowp_tables(m->ref, op32, opbf);
 
   int prev = 0;
   hipGetDevice(&prev);
@@ -212,6 +272,8 @@ extern "C" dg_status dg_mesh_create(int order, int64_t n_elem, const double* ele
   dg_status st = up(reinterpret_cast<void**>(&m->d_geo), geo.data(), geo.size() * sizeof(double));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_conn), m->conn_host.data(), m->conn_host.size() * sizeof(int32_t));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_op64), op64.data(), op64.size() * sizeof(double));
+  if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_op32), op32.data(), op32.size() * sizeof(float));
+  if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_opbf), opbf.data(), opbf.size() * sizeof(uint16_t));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_fmask), m->ref.Fmask.data(), m->ref.Fmask.size() * sizeof(int));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_nbtab), m->nbtab.data(), m->nbtab.size());
   hipSetDevice(prev);
@@ -229,6 +291,8 @@ extern "C" dg_status dg_mesh_destroy(dg_mesh h) {
   hipFree(m->d_geo);
   hipFree(m->d_conn);
   hipFree(m->d_op64);
+  hipFree(m->d_op32);
+  hipFree(m->d_opbf);
   hipFree(m->d_fmask);
   hipFree(m->d_nbtab);
   hipSetDevice(prev);

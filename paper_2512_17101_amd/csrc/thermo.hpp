@@ -1,0 +1,38 @@
+// Species and mechanism tables handed to the reacting-flow kernels by value.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/dg.h"
+
+namespace dg {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kMaxReactions = 8;
+constexpr double kRu = 8.314462618;  // J / (mol K)
+constexpr double kTmin = 100.0, kTmax = 6000.0;
+
+struct ThermoTable {
+  int ns;
+  double R[kMaxSpecies];          // R_k = R_u / W_k
+  double W[kMaxSpecies];
+  double h[kMaxSpecies][6];       // h_k/R_k = T (h0 + T (h1 + ...)) + h5: (a1, a2/2, a3/3, a4/4, a5/5, a6)
+  double cp[kMaxSpecies][5];      // cp_k/R_k coefficients (a1 .. a5)
+};
+
+struct MechTable {
+  int ns, nr;
+  double invW[kMaxSpecies];
+  double A[kMaxReactions];
+  double EaR[kMaxReactions];      // Ea_j / R_u
+  int nu_r[kMaxReactions][kMaxSpecies];
+  double Wnet[kMaxSpecies][kMaxReactions];  // W_k (nu''_kj - nu'_kj)
+};
+
+dg_status launch_temperature(const ThermoTable& th, int64_t n, const double* q, const double* Tguess,
+                             double Tdefault, double* Tout, int32_t* iters, double tol, int max_iter, hipStream_t s);
+dg_status launch_sources(const MechTable& mk, int64_t n, const double* q, const double* T, double* omega,
+                         hipStream_t s);
+
+}  // namespace dg

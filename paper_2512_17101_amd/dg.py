@@ -22,7 +22,11 @@ STATUS = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_ALLOC", 4: "
 
 # every symbol include/dg.h declares
 EXPORTS = ("dg_reference_operators", "dg_mesh_create", "dg_mesh_info", "dg_mesh_nodes", "dg_mesh_face_map",
-           "dg_mesh_destroy", "dg_rhs", "dg_rk_step", "dg_lsrk_update", "dg_last_error")
+           "dg_mesh_destroy", "dg_rhs", "dg_rk_step", "dg_lsrk_update", "dg_thermo_create", "dg_thermo_destroy",
+           "dg_mech_create", "dg_mech_destroy", "dg_temperature", "dg_sources", "dg_mlp_create", "dg_mlp_destroy",
+           "dg_mlp_set_params", "dg_mlp_get_params", "dg_mlp_set_normalization", "dg_mlp_get_normalization",
+           "dg_mlp_fit_normalization", "dg_mlp_loss_grad", "dg_mlp_train_step", "dg_mlp_predict",
+           "dg_temperature_learned", "dg_last_error")
 
 
 class DGError(RuntimeError):
@@ -58,6 +62,24 @@ def lib():
         L.dg_rhs.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_int, _c_p, _c_p, _c_p]
         L.dg_rk_step.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_int, _c_p, _c_p, _dbl, _dbl, _c_p]
         L.dg_lsrk_update.argtypes = [_i64, _dbl, _dbl, _dbl, _c_p, _c_p, _c_p, _c_p]
+        L.dg_thermo_create.argtypes = [ctypes.c_int, _c_p, _c_p, ctypes.c_int, ctypes.POINTER(_c_p)]
+        L.dg_thermo_destroy.argtypes = [_c_p]
+        L.dg_mech_create.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, _c_p, ctypes.POINTER(_c_p)]
+        L.dg_mech_destroy.argtypes = [_c_p]
+        L.dg_temperature.argtypes = [_c_p, _i64, _c_p, _c_p, _dbl, _c_p, _c_p, _dbl, ctypes.c_int, _c_p]
+        L.dg_sources.argtypes = [_c_p, _i64, _c_p, _c_p, _c_p, _c_p]
+        L.dg_mlp_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_c_p)]
+        L.dg_mlp_destroy.argtypes = [_c_p]
+        L.dg_mlp_set_params.argtypes = [_c_p, _c_p]
+        L.dg_mlp_get_params.argtypes = [_c_p, _c_p]
+        L.dg_mlp_set_normalization.argtypes = [_c_p, _c_p, _c_p, _dbl, _dbl]
+        L.dg_mlp_get_normalization.argtypes = [_c_p, _c_p, _c_p, _c_p, _c_p]
+        L.dg_mlp_fit_normalization.argtypes = [_c_p, _i64, _i64, _c_p, _c_p, _c_p]
+        L.dg_mlp_loss_grad.argtypes = [_c_p, _i64, _i64, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
+        L.dg_mlp_train_step.argtypes = [_c_p, _i64, _i64, _c_p, _c_p, _c_p, ctypes.c_float, _c_p, _c_p]
+        L.dg_mlp_predict.argtypes = [_c_p, _i64, _i64, _c_p, _c_p, _c_p]
+        L.dg_temperature_learned.argtypes = [_c_p, _c_p, _i64, _c_p, _dbl, _c_p, _c_p, _dbl, ctypes.c_int,
+                                             ctypes.c_int, _c_p, _c_p]
         for name in EXPORTS:
             if name != "dg_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -177,3 +199,163 @@ def lsrk_update(a: float, b: float, dt: float, rhs_t, res, q, stream=None):
     if rhs_t.numel() != n or res.numel() != n:
         raise ValueError("rhs, res and q must have the same size")
     _check(lib().dg_lsrk_update(n, a, b, dt, _dev_ptr(rhs_t), _dev_ptr(res), _dev_ptr(q), _stream(stream)))
+
+
+class Thermo:
+    """Owning wrapper of a dg_thermo handle (species table)."""
+
+    def __init__(self, W, coeffs, device: int = 0):
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        a = np.ascontiguousarray(coeffs, dtype=np.float64)
+        if a.shape != (W.shape[0], 6):
+            raise ValueError("coeffs must be [n_species, 6]")
+        h = ctypes.c_void_p()
+        _check(lib().dg_thermo_create(W.shape[0], _np_ptr(W), _np_ptr(a), device, ctypes.byref(h)))
+        self._h, self.ns, self.device = h, W.shape[0], device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dg_thermo_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mechanism:
+    """Owning wrapper of a dg_mech handle (irreversible Arrhenius reactions)."""
+
+    def __init__(self, thermo: Thermo, A, Ea, nu_r, nu_p):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        Ea = np.ascontiguousarray(Ea, dtype=np.float64)
+        nr = np.ascontiguousarray(nu_r, dtype=np.int32)
+        npr = np.ascontiguousarray(nu_p, dtype=np.int32)
+        if nr.shape != (A.shape[0], thermo.ns) or npr.shape != nr.shape or Ea.shape != A.shape:
+            raise ValueError("A, Ea [nr]; nu_r, nu_p [nr, ns]")
+        h = ctypes.c_void_p()
+        _check(lib().dg_mech_create(thermo.handle, A.shape[0], _np_ptr(A), _np_ptr(Ea), _np_ptr(nr), _np_ptr(npr),
+                                    ctypes.byref(h)))
+        self._h, self.ns, self.nr = h, thermo.ns, A.shape[0]
+        self._thermo = thermo
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dg_mech_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def temperature(thermo: Thermo, q, T_out, iters, T_guess=None, T_default: float = 1000.0, tol: float = 1e-10,
+                max_iter: int = 50, stream=None):
+    """Newton temperature of the reacting state q ([5+ns, ...] float64 device
+    tensor); T_out float64 and iters int32 device tensors of q[0]'s size."""
+    n = q[0].numel()
+    if q.shape[0] != 5 + thermo.ns or T_out.numel() != n or iters.numel() != n:
+        raise ValueError("q must be [5+ns, ...]; T_out and iters sized like one field")
+    g = _dev_ptr(T_guess) if T_guess is not None else ctypes.c_void_p()
+    _check(lib().dg_temperature(thermo.handle, n, _dev_ptr(q), g, float(T_default), _dev_ptr(T_out),
+                                _dev_ptr(iters, "int32"), float(tol), int(max_iter), _stream(stream)))
+
+
+def sources(mech: Mechanism, q, T, omega, stream=None):
+    """Species mass sources omega [ns, ...] from q [5+ns, ...] and T."""
+    n = q[0].numel()
+    if q.shape[0] != 5 + mech.ns or T.numel() != n or omega.numel() != mech.ns * n:
+        raise ValueError("q [5+ns, ...], T [...], omega [ns, ...]")
+    _check(lib().dg_sources(mech.handle, n, _dev_ptr(q), _dev_ptr(T), _dev_ptr(omega), _stream(stream)))
+
+
+N_MLP_PARAMS = 9025
+
+
+class MLP:
+    """Owning wrapper of a dg_mlp handle (learned temperature guess)."""
+
+    def __init__(self, device: int = 0, seed: int = 4002):
+        h = ctypes.c_void_p()
+        _check(lib().dg_mlp_create(device, seed, ctypes.byref(h)))
+        self._h, self.device = h, device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != N_MLP_PARAMS:
+            raise ValueError("expected 9025 parameters")
+        _check(lib().dg_mlp_set_params(self._h, _np_ptr(p)))
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(N_MLP_PARAMS, dtype=np.float32)
+        _check(lib().dg_mlp_get_params(self._h, _np_ptr(p)))
+        return p
+
+    def set_normalization(self, mean, std, T_mean, T_std):
+        m = np.ascontiguousarray(mean, dtype=np.float64)
+        s_ = np.ascontiguousarray(std, dtype=np.float64)
+        _check(lib().dg_mlp_set_normalization(self._h, _np_ptr(m), _np_ptr(s_), float(T_mean), float(T_std)))
+
+    def get_normalization(self):
+        m, s_ = np.zeros(9), np.zeros(9)
+        tm, ts = ctypes.c_double(), ctypes.c_double()
+        _check(lib().dg_mlp_get_normalization(self._h, _np_ptr(m), _np_ptr(s_), ctypes.byref(tm), ctypes.byref(ts)))
+        return m, s_, tm.value, ts.value
+
+    def fit_normalization(self, q, idx, T):
+        ld = q[0].numel()
+        _check(lib().dg_mlp_fit_normalization(self._h, idx.numel(), ld, _dev_ptr(q), _dev_ptr(idx, "int64"),
+                                              _dev_ptr(T)))
+
+    def loss_grad(self, q, idx, T, grad=None, loss=None, stream=None):
+        ld = q[0].numel()
+        g = _dev_ptr(grad, "float32") if grad is not None else ctypes.c_void_p()
+        l_ = _dev_ptr(loss, "float32") if loss is not None else ctypes.c_void_p()
+        _check(lib().dg_mlp_loss_grad(self._h, idx.numel(), ld, _dev_ptr(q), _dev_ptr(idx, "int64"), _dev_ptr(T),
+                                      g, l_, _stream(stream)))
+
+    def train_step(self, q, idx, T, lr=1e-3, loss=None, stream=None):
+        ld = q[0].numel()
+        l_ = _dev_ptr(loss, "float32") if loss is not None else ctypes.c_void_p()
+        _check(lib().dg_mlp_train_step(self._h, idx.numel(), ld, _dev_ptr(q), _dev_ptr(idx, "int64"), _dev_ptr(T),
+                                       float(lr), l_, _stream(stream)))
+
+    def predict(self, q, out, stream=None):
+        n = q[0].numel()
+        _check(lib().dg_mlp_predict(self._h, n, n, _dev_ptr(q), _dev_ptr(out), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dg_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def temperature_learned(thermo: Thermo, mlp: MLP, q, T_out, iters, T_default: float = 1000.0, tol: float = 1e-10,
+                        max_iter: int = 50, learned_max_iter: int = 8, fallback_count=None, stream=None):
+    n = q[0].numel()
+    fb = _dev_ptr(fallback_count, "int32") if fallback_count is not None else ctypes.c_void_p()
+    _check(lib().dg_temperature_learned(thermo.handle, mlp.handle, n, _dev_ptr(q), float(T_default),
+                                        _dev_ptr(T_out), _dev_ptr(iters, "int32"), float(tol), int(max_iter),
+                                        int(learned_max_iter), fb, _stream(stream)))

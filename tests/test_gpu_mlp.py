@@ -1,0 +1,173 @@
+"""GPU learned temperature guess (BF16 matrix-core MLP) against the oracle,
+through the C ABI: forward against the BF16-emulating oracle, gradients within
+1e-3 relative L2 per tensor of the emulating oracle (FP64 reported), Adam's
+update rule, normalisation fit, and the learned Newton start leaving the
+converged temperature unchanged (<= 1e-9 K) while cutting iterations."""
+import numpy as np
+import pytest
+
+from oracle import mesh as om, mlp as omlp, reference_element as ore, thermo as ot
+from paper_2512_17101_amd import dg, workload as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TH = wl.synthetic_thermo(3003)
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _flat(params):
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
+
+
+def _unflat(p):
+    out, o = [], 0
+    for fi, fo in ((9, 64), (64, 64), (64, 64), (64, 1)):
+        W = p[o:o + fi * fo].reshape(fo, fi).astype(np.float64)
+        o += fi * fo
+        b = p[o:o + fo].astype(np.float64)
+        o += fo
+        out.append((W, b))
+    return out
+
+
+def _data(n_cells=8, seeds=(3005,)):
+    qs = []
+    for sd in seeds:
+        xyz, _ = wl.kuhn_box_mesh(n_cells, 0.01, 0.03, 1003)
+        X = om.node_coordinates(xyz, ore.nodes(3)).reshape(-1, 3)
+        qs.append(wl.reacting_state(X, seed=sd, n_cells=n_cells))
+    q = np.ascontiguousarray(np.concatenate(qs, axis=1))
+    rho, u, v, w, e, Y = ot.primitives(q)
+    T, it = ot.newton_temperature(e, Y, TH, 1000.0)
+    assert np.all(it > 0)
+    return q, T
+
+
+def _norm(q, T):
+    return omlp.normalization(omlp.features(q), T)
+
+
+def _round_params(params):
+    # the device keeps FP32 masters
+    return [(W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)) for W, b in params]
+
+
+def test_predict_matches_bf16_oracle():
+    dev = _dev()
+    q_np, T_np = _data()
+    params = _round_params(omlp.init_params(11))
+    params = [(W, b + 0.1 * np.random.default_rng(i).standard_normal(b.shape)) for i, (W, b) in enumerate(params)]
+    params = _round_params(params)
+    mean, std, tm, ts = _norm(q_np, T_np)
+    net = dg.MLP()
+    net.set_params(_flat(params))
+    net.set_normalization(mean, std, tm, ts)
+    q = torch.from_numpy(q_np).to(dev)
+    out = torch.empty(q.shape[1], dtype=torch.float64, device=dev)
+    net.predict(q, out)
+    torch.cuda.synchronize()
+    X = (omlp.features(q_np) - mean) / std
+    ref, _ = omlp.forward(params, X, "bf16")
+    got = (out.cpu().numpy() - tm) / ts
+    d = got - ref
+    print("predict: rel L2", np.linalg.norm(d) / np.linalg.norm(ref), "max", np.abs(d).max())
+    assert np.linalg.norm(d) <= 5e-3 * np.linalg.norm(ref)
+    assert np.abs(d).max() <= 0.05
+
+
+def test_gradients_match_bf16_oracle():
+    dev = _dev()
+    q_np, T_np = _data()
+    params = _round_params(omlp.init_params(12))
+    mean, std, tm, ts = _norm(q_np, T_np)
+    net = dg.MLP()
+    net.set_params(_flat(params))
+    net.set_normalization(mean, std, tm, ts)
+    rng = np.random.default_rng(5)
+    idx_np = rng.choice(q_np.shape[1], 1000, replace=False).astype(np.int64)  # not a multiple of 32
+    q = torch.from_numpy(q_np).to(dev)
+    T = torch.from_numpy(T_np).to(dev)
+    idx = torch.from_numpy(idx_np).to(dev)
+    g = torch.empty(dg.N_MLP_PARAMS, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    net.loss_grad(q, idx, T, grad=g, loss=loss)
+    torch.cuda.synchronize()
+    X = (omlp.features(q_np)[idx_np] - mean) / std
+    y = (T_np[idx_np] - tm) / ts
+    l16, g16 = omlp.loss_and_grads(params, X, y, "bf16")
+    l64, g64 = omlp.loss_and_grads(params, X, y, "fp64")
+    got = _unflat(g.cpu().numpy())
+    assert abs(loss.item() - l16) <= 1e-3 * l16
+    for li in range(4):
+        for j in range(2):
+            a, r16, r64 = got[li][j], g16[li][j], g64[li][j]
+            e16 = np.linalg.norm(a - r16) / np.linalg.norm(r16)
+            e64 = np.linalg.norm(a - r64) / np.linalg.norm(r64)
+            print(f"layer {li + 1} {'W' if j == 0 else 'b'}: rel L2 vs bf16 oracle {e16:.2e}, vs fp64 {e64:.2e}")
+            assert e16 <= 1e-3
+
+
+def test_adam_step_rule_and_normalization_fit():
+    dev = _dev()
+    q_np, T_np = _data()
+    net = dg.MLP(seed=7)
+    q = torch.from_numpy(q_np).to(dev)
+    T = torch.from_numpy(T_np).to(dev)
+    idx = torch.arange(0, q_np.shape[1], 3, dtype=torch.int64, device=dev)
+    net.fit_normalization(q, idx, T)
+    mean, std, tm, ts = net.get_normalization()
+    ii = idx.cpu().numpy()
+    m_ref, s_ref, tm_ref, ts_ref = omlp.normalization(omlp.features(q_np)[ii], T_np[ii])
+    np.testing.assert_allclose(mean, m_ref, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(std, s_ref, rtol=1e-6)
+    np.testing.assert_allclose([tm, ts], [tm_ref, ts_ref], rtol=1e-8)
+    p0 = net.get_params()
+    g = torch.empty(dg.N_MLP_PARAMS, dtype=torch.float32, device=dev)
+    bidx = idx[:512]
+    net.loss_grad(q, bidx, T, grad=g)
+    net.train_step(q, bidx, T, lr=1e-3)
+    torch.cuda.synchronize()
+    p1 = net.get_params()
+    gg = g.cpu().numpy().astype(np.float64)
+    expect = p0 - 1e-3 * gg / (np.abs(gg) + 1e-8)  # Adam's first step, bias-corrected
+    np.testing.assert_allclose(p1, expect, rtol=0, atol=2e-7)
+
+
+def test_learned_guess_cuts_iterations_and_keeps_answers():
+    dev = _dev()
+    q_np, T_np = _data(n_cells=8, seeds=(3005, 3105, 3205))
+    q = torch.from_numpy(q_np).to(dev)
+    T = torch.from_numpy(T_np).to(dev)
+    th = dg.Thermo(TH["W"], TH["a"])
+    net = dg.MLP(seed=4002)
+    n = q_np.shape[1]
+    idx_all = torch.randperm(n, generator=torch.Generator().manual_seed(4003))
+    net.fit_normalization(q, idx_all.to(dev), T)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    for it in range(400):
+        bi = idx_all[(it * 2048) % (n - 2048):(it * 2048) % (n - 2048) + 2048].to(dev)
+        net.train_step(q, bi, T, lr=2e-3, loss=loss)
+    torch.cuda.synchronize()
+    print("final batch loss", loss.item())
+    # evaluate on a state the network has not seen
+    q2_np, T2_np = _data(n_cells=8, seeds=(3999,))
+    q2 = torch.from_numpy(q2_np).to(dev)
+    n2 = q2_np.shape[1]
+    Tp, ip = torch.empty(n2, dtype=torch.float64, device=dev), torch.empty(n2, dtype=torch.int32, device=dev)
+    Tl, il = torch.empty_like(Tp), torch.empty_like(ip)
+    fb = torch.zeros(1, dtype=torch.int32, device=dev)
+    dg.temperature(th, q2, Tp, ip, T_default=1000.0)
+    dg.temperature_learned(th, net, q2, Tl, il, T_default=1000.0, learned_max_iter=8, fallback_count=fb)
+    torch.cuda.synchronize()
+    Tp, ip, Tl, il = Tp.cpu().numpy(), ip.cpu().numpy(), Tl.cpu().numpy(), il.cpu().numpy()
+    print(f"mean iterations plain {ip.mean():.3f} learned {il.mean():.3f} fallbacks {fb.item()} / {n2}")
+    assert np.all(ip > 0) and np.all(il > 0)
+    assert np.abs(Tl - Tp).max() <= 1e-9
+    assert np.abs(Tl - T2_np).max() <= 1e-9
+    assert il.mean() < ip.mean()

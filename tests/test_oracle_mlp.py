@@ -78,3 +78,12 @@ def test_training_reduces_loss():
         p = opt.step(p, g)
     l1, _ = mlp.loss_and_grads(p, X, y, "bf16")
     assert l1 < 0.1 * l0
+
+
+def test_normalization_centres_constant_features():
+    rng = np.random.default_rng(9)
+    F = rng.standard_normal((500, 9))
+    F[:, 8] = 0.72  # constant (inert species)
+    mean, std, tm, ts = mlp.normalization(F, rng.uniform(300, 2000, 500))
+    assert std[8] == 1.0 and abs(mean[8] - 0.72) < 1e-13
+    np.testing.assert_allclose(std[:8], F[:, :8].std(0))
