@@ -20,6 +20,7 @@
 // Fused Runge-Kutta epilogue (stage of the 2N-storage scheme):
 //   res <- a res + dt rhs;  q_out <- q + b res   (q_out is a second buffer,
 //   because neighbouring tiles still read q).
+#include "euler_point.hpp"
 #include "internal.hpp"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -54,25 +55,70 @@ struct RhsArgs {
   double gamma, a, b, dt;
 };
 
+// Waves per block: the per-wave state tile lives in LDS (5 fields x 16
+// elements x Np doubles), so order 4 uses two-wave blocks.
+template <int P>
+struct Tiling {
+  using C = Cfg<P>;
+  static constexpr int WAVES = P >= 4 ? 2 : 4;
+  static constexpr int TQ = 16 * C::NP;  // doubles of one field of one tile
+  static constexpr int OP = (3 * C::KV + C::KL) * C::NRB * 64;
+  static constexpr bool OP_IN_LDS = OP * 8 <= 32 * 1024;
+  static constexpr int OP_LDS = OP_IN_LDS ? OP : 1;
+};
+
 template <int P, bool FUSED>
 __global__ __launch_bounds__(256) void rhs_euler_fp64_kernel(RhsArgs A) {
   using C = Cfg<P>;
+  using TL = Tiling<P>;
   constexpr int NB16 = C::NB16 > 0 ? C::NB16 : 1;
   constexpr int NB4 = C::NB4 > 0 ? C::NB4 : 1;
+  __shared__ double s_q[TL::WAVES][5 * TL::TQ];
+  __shared__ double s_op[TL::OP_LDS];
+  __shared__ uint8_t s_nb[4 * 24 * C::NFP];
+  __shared__ int s_fm[4 * C::NFP];
+  for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nb[i] = A.nbtab[i];
+  for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fm[i] = A.fmask[i];
+  if (TL::OP_IN_LDS)
+    for (int i = threadIdx.x; i < TL::OP; i += blockDim.x) s_op[i] = A.op[i];
+  __syncthreads();
+  const double* __restrict__ op = TL::OP_IN_LDS ? s_op : A.op;
+
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (tile >= A.ntiles) return;  // uniform per wave
+  const int wave = threadIdx.x >> 6;
+  const int tile = blockIdx.x * TL::WAVES + wave;
+  if (tile >= A.ntiles) return;  // uniform per wave; no block barrier follows
   const int n = lane & 15, g = lane >> 4;
-  const int64_t e = static_cast<int64_t>(tile) * 16 + n;
+  const int64_t e0 = static_cast<int64_t>(tile) * 16;
+  const int64_t e = e0 + n;
   const bool valid = e < A.E;
   const int64_t ec = valid ? e : A.E - 1;
   const int64_t Es = A.E * C::NP;
   const double* __restrict__ q = A.q;
   const double gm1 = A.gamma - 1.0;
+  double* sq = s_q[wave];
 
+  // stage this tile's state (coalesced: each field's tile block is contiguous)
+  {
+    const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const double* src = q + f * Es + e0 * C::NP;
+#pragma unroll
+      for (int k = 0; k < (TL::TQ + 63) / 64; ++k) {
+        const int i = 64 * k + lane;
+        if (i < nval) sq[f * TL::TQ + i] = src[i];
+      }
+    }
+  }
   double gm[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) gm[c] = A.geo[c * A.Epad + ec];
+  int2 cn[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) cn[f] = A.conn[f * A.Epad + ec];
+  __builtin_amdgcn_wave_barrier();
+  const int nl = valid ? n : static_cast<int>(ec - e0);  // element row in the tile
 
   v4d acc16[5][NB16];
   double acc4[5][NB4];
@@ -92,19 +138,8 @@ __global__ __launch_bounds__(256) void rhs_euler_fp64_kernel(RhsArgs A) {
     if (j < C::NP) {
       double qq[5];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) qq[f] = q[f * Es + ec * C::NP + j];
-      const double ir = 1.0 / qq[0];
-      const double u = qq[1] * ir, v = qq[2] * ir, w = qq[3] * ir;
-      const double p = gm1 * (qq[4] - 0.5 * (qq[1] * u + qq[2] * v + qq[3] * w));
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const double U = gm[3 * r] * u + gm[3 * r + 1] * v + gm[3 * r + 2] * w;
-        G[r][0] = qq[0] * U;
-        G[r][1] = qq[1] * U + p * gm[3 * r];
-        G[r][2] = qq[2] * U + p * gm[3 * r + 1];
-        G[r][3] = qq[3] * U + p * gm[3 * r + 2];
-        G[r][4] = (qq[4] + p) * U;
-      }
+      for (int f = 0; f < 5; ++f) qq[f] = sq[f * TL::TQ + nl * C::NP + j];
+      contravariant_flux(qq, gm, gm1, G);
     } else {
 #pragma unroll
       for (int r = 0; r < 3; ++r)
@@ -115,7 +150,7 @@ __global__ __launch_bounds__(256) void rhs_euler_fp64_kernel(RhsArgs A) {
     for (int r = 0; r < 3; ++r) {
 #pragma unroll
       for (int rb = 0; rb < C::NRB; ++rb) {
-        const double a = A.op[((r * C::KV + s) * C::NRB + rb) * 64 + lane];
+        const double a = op[((r * C::KV + s) * C::NRB + rb) * 64 + lane];
         if (rb < C::NB16) {
 #pragma unroll
           for (int f = 0; f < 5; ++f)
@@ -129,45 +164,32 @@ __global__ __launch_bounds__(256) void rhs_euler_fp64_kernel(RhsArgs A) {
     }
   }
 
-  // ---- surface: Lax-Friedrichs jump at face node fm = 4 s + g, contracted with LIFT
+  // ---- surface: Lax-Friedrichs jump at face node fm = 4 s + g, contracted with LIFT;
+  // own traces from the staged tile, neighbour traces from it when the
+  // neighbour is in the tile, else from memory
 #pragma unroll
   for (int s = 0; s < C::KL; ++s) {
     const int fm = 4 * s + g;
     const int face = fm / C::NFP;
     const int mm = fm - face * C::NFP;
-    const int own = A.fmask[fm];
-    const int2 cn = A.conn[face * A.Epad + ec];
-    const int jp = A.nbtab[(face * 24 + cn.y) * C::NFP + mm];
+    const int own = s_fm[fm];
+    const int2 c = face == 0 ? cn[0] : face == 1 ? cn[1] : face == 2 ? cn[2] : cn[3];
+    const int jp = s_nb[(face * 24 + c.y) * C::NFP + mm];
+    const int64_t nloc = static_cast<int64_t>(c.x) - e0;
+    const bool in_tile = nloc >= 0 && nloc < 16;
     double qm[5], qp[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      qm[f] = q[f * Es + ec * C::NP + own];
-      qp[f] = q[f * Es + static_cast<int64_t>(cn.x) * C::NP + jp];
+      qm[f] = sq[f * TL::TQ + nl * C::NP + own];
+      qp[f] = in_tile ? sq[f * TL::TQ + static_cast<int>(nloc) * C::NP + jp]
+                      : q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
     }
-    double Nx, Ny, Nz;
-    if (face == 0) { Nx = -gm[6]; Ny = -gm[7]; Nz = -gm[8]; }
-    else if (face == 1) { Nx = -gm[3]; Ny = -gm[4]; Nz = -gm[5]; }
-    else if (face == 2) { Nx = gm[0] + gm[3] + gm[6]; Ny = gm[1] + gm[4] + gm[7]; Nz = gm[2] + gm[5] + gm[8]; }
-    else { Nx = -gm[0]; Ny = -gm[1]; Nz = -gm[2]; }
-    const double Fs = sqrt(Nx * Nx + Ny * Ny + Nz * Nz);
-    const double irm = 1.0 / qm[0], irp = 1.0 / qp[0];
-    const double um = qm[1] * irm, vm = qm[2] * irm, wm = qm[3] * irm;
-    const double up = qp[1] * irp, vp = qp[2] * irp, wp = qp[3] * irp;
-    const double pm = gm1 * (qm[4] - 0.5 * (qm[1] * um + qm[2] * vm + qm[3] * wm));
-    const double pp = gm1 * (qp[4] - 0.5 * (qp[1] * up + qp[2] * vp + qp[3] * wp));
-    const double Unm = Nx * um + Ny * vm + Nz * wm;
-    const double Unp = Nx * up + Ny * vp + Nz * wp;
-    const double cm = sqrt(A.gamma * pm * irm), cp = sqrt(A.gamma * pp * irp);
-    const double lamFs = fmax(fabs(Unm) + cm * Fs, fabs(Unp) + cp * Fs);
-    double D[5];
-    D[0] = 0.5 * (qm[0] * Unm - qp[0] * Unp) - 0.5 * lamFs * (qm[0] - qp[0]);
-    D[1] = 0.5 * (qm[1] * Unm + pm * Nx - qp[1] * Unp - pp * Nx) - 0.5 * lamFs * (qm[1] - qp[1]);
-    D[2] = 0.5 * (qm[2] * Unm + pm * Ny - qp[2] * Unp - pp * Ny) - 0.5 * lamFs * (qm[2] - qp[2]);
-    D[3] = 0.5 * (qm[3] * Unm + pm * Nz - qp[3] * Unp - pp * Nz) - 0.5 * lamFs * (qm[3] - qp[3]);
-    D[4] = 0.5 * ((qm[4] + pm) * Unm - (qp[4] + pp) * Unp) - 0.5 * lamFs * (qm[4] - qp[4]);
+    double Nx, Ny, Nz, D[5];
+    scaled_normal(face, gm, Nx, Ny, Nz);
+    lf_jump(qm, qp, Nx, Ny, Nz, A.gamma, D);
 #pragma unroll
     for (int rb = 0; rb < C::NRB; ++rb) {
-      const double a = A.op[((3 * C::KV + s) * C::NRB + rb) * 64 + lane];
+      const double a = op[((3 * C::KV + s) * C::NRB + rb) * 64 + lane];
       if (rb < C::NB16) {
 #pragma unroll
         for (int f = 0; f < 5; ++f)
@@ -182,33 +204,25 @@ __global__ __launch_bounds__(256) void rhs_euler_fp64_kernel(RhsArgs A) {
 
   // ---- store: lane (n, g) holds rows 16 rb + 4 v + g and 16 NB16 + 4 rb4 + g
   if (!valid) return;
-  auto put = [&](int f, int row, double val) {
-    const int64_t idx = f * Es + e * C::NP + row;
-    if (!FUSED) {
-      A.rhs[idx] = val;
-    } else {
-      const double r = (A.a == 0.0 ? 0.0 : A.a * A.res[idx]) + A.dt * val;
-      A.res[idx] = r;
-      A.qout[idx] = q[idx] + A.b * r;
-    }
-  };
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
 #pragma unroll
     for (int rb = 0; rb < C::NB16; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) put(f, 16 * rb + 4 * v + g, acc16[f][rb][v]);
+      for (int v = 0; v < 4; ++v)
+        emit<FUSED>(f * Es + e * C::NP + 16 * rb + 4 * v + g, acc16[f][rb][v], A.rhs, A.res, A.qout, q, A.a, A.b,
+                    A.dt);
 #pragma unroll
     for (int rb = 0; rb < C::NB4; ++rb) {
       const int row = 16 * C::NB16 + 4 * rb + g;
-      if (row < C::NP) put(f, row, acc4[f][rb]);
+      if (row < C::NP) emit<FUSED>(f * Es + e * C::NP + row, acc4[f][rb], A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
     }
   }
 }
 
 template <int P>
 dg_status launch_p(const Mesh& m, const RhsArgs& args, bool fused, hipStream_t s) {
-  const int waves = 4;
+  const int waves = Tiling<P>::WAVES;
   const int blocks = (args.ntiles + waves - 1) / waves;
   if (fused)
     rhs_euler_fp64_kernel<P, true><<<blocks, 64 * waves, 0, s>>>(args);
