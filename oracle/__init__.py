@@ -18,4 +18,8 @@ Modules:
   mesh               affine geometry, face normals/areas, face-node connectivity
   euler              strong-form Euler RHS with a local Lax-Friedrichs flux
   lsrk               five-stage, fourth-order low-storage Runge-Kutta
+  precision          FP32 / split-BF16 contraction emulation and error bounds
+  thermo             mixture thermodynamics, temperature Newton, Arrhenius sources
+  mlp                learned temperature guess (forward, backward, Adam)
+  ns                 reacting Navier-Stokes right-hand side with BR1 viscous terms
 """
