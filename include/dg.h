@@ -26,7 +26,8 @@
  *    aligned at least (256-byte recommended); the library never frees them and
  *    keeps no pointer past return.  Compute calls are asynchronous on the given
  *    HIP stream (0 = the null stream); argument checks are synchronous.
- *  - Handles (dg_mesh, dg_thermo, dg_mech) own their tables; *_destroy frees them.
+ *  - Handles (dg_mesh, dg_thermo, dg_mech, dg_mlp, dg_batch) own their tables;
+ *    *_destroy frees them.
  *    A handle is immutable after creation, so calls on different streams may
  *    share it.
  */
@@ -56,9 +57,15 @@ typedef enum {
  * in every mode. */
 typedef enum { DG_FP64 = 0, DG_FP32 = 1, DG_SPLIT_BF16 = 2 } dg_precision;
 
+struct dg_thermo_s;
+struct dg_mech_s;
+
 typedef struct {
-  int model;      /* 0 = Euler (ideal gas); other values are rejected */
-  double gamma;   /* ratio of specific heats, > 1 */
+  int model;      /* 0 = Euler (ideal gas), 1 = reacting Navier-Stokes (dg_ns_*) */
+  double gamma;   /* Euler: ratio of specific heats, > 1 (unused by model 1) */
+  double mu, Pr, Sc;                 /* model 1: viscosity [Pa s] >= 0, Prandtl and Schmidt numbers > 0 */
+  const struct dg_thermo_s* thermo;  /* model 1: species thermodynamics (7 species), required */
+  const struct dg_mech_s* mech;      /* model 1: reactions; NULL = no chemical sources */
 } dg_params;
 
 typedef struct dg_mesh_s* dg_mesh;
@@ -208,6 +215,101 @@ dg_status dg_mlp_predict(dg_mlp m, int64_t n, int64_t ld, const double* q, doubl
 dg_status dg_temperature_learned(dg_thermo th, dg_mlp m, int64_t n, const double* q, double T_default,
                                  double* T_out, int32_t* iters, double tol, int max_iter, int learned_max_iter,
                                  int32_t* fallback_count, hipStream_t stream);
+
+/* ---- reacting Navier-Stokes with BR1 viscous terms ---------------------- */
+/* Viscous, multispecies, reacting flow as named for MIRGE-Com (Sec. 5); the
+ * paper prints no equation, so the textbook forms are used.  State
+ * q[12][E][Np] (rho, rho u, rho v, rho w, E_total, rho Y_1 .. rho Y_7) with
+ * temperatures T[E][Np] from dg_temperature; p = rho R_mix T.  Viscous
+ * terms by Bassi & Rebay's first scheme: lifted gradients of
+ * v = (u, v, w, T, Y_1 .. Y_7) with the central trace,
+ *   sigma_d(v) = sum_a (da/dx_d) D_a v + LIFT( Fscale n_d (v+ - v-) / 2 ),
+ * stored as sigma[3 c + d][E][Np]; stress tau = mu (grad u + grad u^T
+ * - 2/3 div u I), heat flux -kappa grad T with kappa = mu cp / Pr, species
+ * flux J_k = -(mu / Sc) grad Y_k; viscous flux (0, tau, u.tau + kappa grad T
+ * - sum_k h_k J_k, -J_k).  Total flux F = F_inviscid - F_viscous; surface
+ * flux: local Lax-Friedrichs on the inviscid part (sound speed from
+ * gamma_mix = cp / cv), central average on the viscous part, no penalty:
+ *   rhs = -sum_a D_a (sum_d da/dx_d F_d) + LIFT( Fscale [ n.(F- - F+) / 2
+ *         - lam (q- - q+) / 2 ] ) + (0, 0, 0, 0, 0, omega_1 .. omega_7),
+ * omega from dg_sources when prm->mech is set.  prm->model must be 1 and
+ * prm->thermo (and mech, if given) must hold 7 species on the mesh's device.
+ * Errors: DG_ERR_ARG for bad parameters, pointers or aliasing,
+ * DG_ERR_UNSUPPORTED for a species count other than 7. */
+
+/* sigma (device [33][E][Np]) receives the lifted gradients; rhs (device
+ * [12][E][Np]) the right-hand side.  q, T, sigma and rhs must not overlap. */
+dg_status dg_ns_rhs(dg_mesh m, const dg_params* prm, const double* q, const double* T, double* sigma, double* rhs,
+                    hipStream_t stream);
+/* One LSRK(5,4) step of the reacting NS system, each stage: temperature
+ * Newton (started from T, tolerance tol, at most max_iter steps), gradient
+ * pass, right-hand side fused with the stage update.  q (device
+ * [12][E][Np]) is updated in place; T (device [E][Np]) is the first stage's
+ * Newton start and returns the temperatures of the last stage's input.
+ * work: device scratch of 58 E Np doubles (residual, second state buffer,
+ * gradients; the last E Np doubles hold the last stage's int32 Newton
+ * iteration counts, -1 where it did not converge). */
+dg_status dg_ns_rk_step(dg_mesh m, const dg_params* prm, double* q, double* T, double* work, double dt, double tol,
+                        int max_iter, hipStream_t stream);
+
+/* ---- batched stepping of many meshes ------------------------------------ */
+/* A batch advances many independent meshes of mixed order (p = 1..4) and
+ * size with one kernel launch per Runge-Kutta stage: a work list holds one
+ * item per (mesh, 16-element tile) of every mesh, and a persistent kernel
+ * walks it, running each item with that mesh's order.  This is the launch
+ * counterpart of concatenating independent calls into one larger call
+ * (Sec. 4.2, "Concatenation of Function Calls"), aimed at the per-launch floor
+ * that small meshes hit (Sec. 5.2, MIRGE-Com vs. MFEM).  Each mesh's result is
+ * bitwise the one dg_rk_step gives it alone at the same precision, because
+ * both run the same tile routine.  Contractions are DG_FP32 or DG_SPLIT_BF16
+ * (DG_FP64 returns DG_ERR_UNSUPPORTED); the state and stage update are FP64.
+ * A batch keeps pointers to the bound caller buffers (and, once a step was
+ * run with use_graph, a captured graph that holds them): they must stay
+ * valid until the next bind or destroy.  Calls on one batch must not
+ * overlap. */
+typedef struct dg_batch_s* dg_batch;
+
+/* Launch shape of the batched stage kernel. */
+typedef struct {
+  int waves_per_block; /* 2, 4 or 8 (64 lanes each) */
+  int blocks_per_cu;   /* 1..4, capped by the kernel's occupancy */
+  int order;           /* work-list order: 0 = highest order first, 1 = mesh order */
+  int xcd_chunks;      /* 1 = each of the 8 XCDs walks a contiguous eighth of the
+                          list, 0 = the whole grid strides over the list */
+} dg_batch_config;
+
+/* Meshes (n >= 1, all on the same device, not freed while the batch lives)
+ * and the contraction precision.  Builds and uploads the work lists; the
+ * initial launch shape is {4, 2, 0, 0}. */
+dg_status dg_batch_create(const dg_mesh* meshes, int n, dg_precision prec, dg_batch* out);
+dg_status dg_batch_destroy(dg_batch b);
+/* Bind the state of every mesh: q[i] device [5][E_i][Np_i] (updated in
+ * place by each step), work[i] device scratch of 2 * 5 * E_i * Np_i doubles
+ * (not overlapping q[i]), dt device [n] time steps (read by every step, so
+ * the caller may change them between steps).  q and work are host arrays of n
+ * device pointers.  Drops a captured graph.  Synchronous. */
+dg_status dg_batch_bind(dg_batch b, double* const* q, double* const* work, const double* dt);
+dg_status dg_batch_set_config(dg_batch b, const dg_batch_config* cfg);
+dg_status dg_batch_get_config(dg_batch b, dg_batch_config* cfg);
+/* One LSRK(5,4) step of every bound mesh: five stage launches and one copy
+ * launch.  use_graph != 0 replays a graph of those six launches on `stream`,
+ * capturing it first when none matches the current binding, configuration
+ * and gamma; use_graph == 0 launches them directly. */
+dg_status dg_batch_rk_step(dg_batch b, const dg_params* prm, int use_graph, hipStream_t stream);
+/* Work items, total elements, and kernel nodes of the captured graph (0 when
+ * none is held).  Any pointer may be NULL. */
+dg_status dg_batch_info(dg_batch b, int64_t* n_items, int64_t* n_elem, int* graph_kernel_nodes);
+/* Time every candidate launch shape (waves_per_block x blocks_per_cu x order
+ * x xcd_chunks) with `trials` steps each after one warm-up step on the bound
+ * buffers, keep the fastest and set it.  The bound q are saved before and
+ * restored after (a temporary device copy), so tuning leaves the state as it
+ * was; work is overwritten.  With cache_path != NULL the choice is looked up
+ * first in that JSON file under a key of (device, precision, multiset of
+ * (p, E)) and, when tuned, written back.  chosen (may be NULL) receives the
+ * shape; best_ms (may be NULL) its time per step (negative when taken from
+ * the cache without timing).  Synchronous on `stream`. */
+dg_status dg_batch_autotune(dg_batch b, const dg_params* prm, const char* cache_path, int trials,
+                            dg_batch_config* chosen, double* best_ms, hipStream_t stream);
 
 const char* dg_last_error(void);
 

@@ -21,18 +21,18 @@ dg_status hip_fail(hipError_t e, const char* what) {
   return fail(DG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
+const double kLsrkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                          -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kLsrkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                          1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                          2277821191437.0 / 14882151754819.0};
+
 }  // namespace dg
 
 using namespace dg;
 
 namespace {
-
-// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
-const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
-                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
-const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
-                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
-                        2277821191437.0 / 14882151754819.0};
 
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
@@ -44,16 +44,6 @@ dg_status check_params(const char* who, const dg_params* prm, dg_precision prec)
     return fail(DG_ERR_ARG, std::string(who) + ": unknown precision");
   return DG_OK;
 }
-
-struct DeviceGuard {
-  int prev = 0;
-  bool ok = false;
-  explicit DeviceGuard(int dev) {
-    hipGetDevice(&prev);
-    ok = hipSetDevice(dev) == hipSuccess;
-  }
-  ~DeviceGuard() { hipSetDevice(prev); }
-};
 
 }  // namespace
 
@@ -107,8 +97,8 @@ extern "C" dg_status dg_rk_step(dg_mesh h, const dg_params* prm, dg_precision pr
     const double* qin = buf[s & 1];
     double* qout = buf[(s + 1) & 1];
     st = prec == DG_FP64
-             ? launch_rhs_euler_fp64(m, prm->gamma, qin, nullptr, res, qout, kRkA[s], kRkB[s], dt, true, stream)
-             : launch_rhs_euler_lowp(m, prec, prm->gamma, qin, nullptr, res, qout, kRkA[s], kRkB[s], dt, true, stream);
+             ? launch_rhs_euler_fp64(m, prm->gamma, qin, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt, true, stream)
+             : launch_rhs_euler_lowp(m, prec, prm->gamma, qin, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt, true, stream);
     if (st != DG_OK) return st;
   }
   // five stages leave the state in the second buffer

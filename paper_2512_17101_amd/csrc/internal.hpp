@@ -15,6 +15,24 @@ namespace dg {
 dg_status fail(dg_status s, const std::string& msg);
 dg_status hip_fail(hipError_t e, const char* what);
 
+// Low-storage five-stage fourth-order Runge-Kutta coefficients
+// (Carpenter & Kennedy 1994): res <- A_s res + dt rhs, q <- q + B_s res.
+extern const double kLsrkA[5];
+extern const double kLsrkB[5];
+
+// Makes `dev` current for its lifetime and restores the previous device.
+struct DeviceGuard {
+  int prev = 0;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    hipGetDevice(&prev);
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() { hipSetDevice(prev); }
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+};
+
 #define DG_HIP(call)                                     \
   do {                                                   \
     hipError_t _e = (call);                              \
@@ -66,6 +84,7 @@ struct Mesh {
   double* d_geo = nullptr;        // [9][Epad] metric terms rx ry rz sx sy sz tx ty tz
   int2* d_conn = nullptr;         // [4][Epad]
   double* d_op64 = nullptr;       // [KS][NRB][64]
+  double* d_opT = nullptr;        // [3 Np + 4 Nfp][Np]: [D_r | D_s | D_t | LIFT] transposed
   float* d_op32 = nullptr;        // FP32 table (LowpLayout)
   uint16_t* d_opbf = nullptr;     // BF16 hi/lo table (LowpLayout)
   int* d_fmask = nullptr;         // [4][Nfp]

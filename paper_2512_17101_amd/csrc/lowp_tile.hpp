@@ -1,0 +1,249 @@
+// One 16-element tile of the Euler right-hand side with reduced-precision
+// element contractions (FP32 or split BF16 on the matrix cores), shared by the
+// single-mesh and the batched multi-mesh kernels.
+//
+// Only the contraction rhs = [-Dr | -Ds | -Dt | LIFT] [G_r; G_s; G_t; Delta]
+// changes precision; fluxes, jumps, the state and the Runge-Kutta stage stay
+// FP64.  One wave owns 16 elements, lane (n, g) = (element, residue mod 4) as
+// in the FP64 kernel; the FP64 operands are rounded where they enter the
+// matrix cores:
+//
+//  FP32        v_mfma_f32_16x16x4f32, K stepped by 4, lane (n, g) supplying
+//              k = 4 ks + g (the same node / face-node mapping as FP64);
+//              rows in 16-row blocks, output row 16 rb + 4 g + v in lane (n, g)
+//              register v.
+//  split BF16  v_mfma_f32_16x16x32_bf16 with x = hi + lo (hi = bf16(x),
+//              lo = bf16(x - hi)) and Op X ~ Op_hi X_hi + Op_hi X_lo +
+//              Op_lo X_hi accumulated in FP32; the split is taken in FP32
+//              (x = fp32 of the FP64 operand).  Each k-step takes 8 slots from
+//              every lane group g; the host permutes the operator's K axis so
+//              that lane group g's slots are exactly the values that lane
+//              computed: volume slots t = 3 s + a (node 4 s + g, direction
+//              a), then face slots t (face node 4 t + g), each padded to a
+//              multiple of 8.
+#pragma once
+#include "euler_point.hpp"
+
+namespace dg {
+namespace lowp {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+
+template <int P>
+struct LCfg {
+  static constexpr int NP = (P + 1) * (P + 2) * (P + 3) / 6;
+  static constexpr int NFP = (P + 1) * (P + 2) / 2;
+  static constexpr int NPP = (NP + 3) / 4 * 4;
+  static constexpr int KV = NPP / 4;        // node steps per lane
+  static constexpr int KL = NFP;            // face-node steps per lane
+  static constexpr int NR = (NP + 15) / 16; // 16-row blocks
+  static constexpr int KS32 = 3 * KV + KL;  // FP32 k-steps (4 wide)
+  static constexpr int VKS = (3 * KV + 7) / 8;  // BF16 volume k-steps (32 wide)
+  static constexpr int FKS = (KL + 7) / 8;      // BF16 face k-steps
+  static constexpr int OP32 = KS32 * NR * 64;        // floats
+  static constexpr int OPBF = (VKS + FKS) * NR * 2 * 64 * 8;  // bf16 values (hi, lo)
+};
+
+struct LowArgs {
+  const double* __restrict__ q;
+  double* __restrict__ rhs;
+  double* __restrict__ res;
+  double* __restrict__ qout;
+  const double* __restrict__ geo;
+  const int2* __restrict__ conn;
+  const float* __restrict__ op32;
+  const uint16_t* __restrict__ opbf;
+  const int* __restrict__ fmask;
+  const uint8_t* __restrict__ nbtab;
+  int64_t E, Epad;
+  int ntiles;
+  double gamma, a, b, dt;
+};
+
+// Splits 8 staged FP32 slots per field into hi = bf16(x) and lo = bf16(x - hi)
+// (round to nearest even; x - hi is exact in FP32), runs the three products
+// Op_hi X_hi + Op_hi X_lo + Op_lo X_hi of k-step k on the matrix cores, and
+// clears the slots.
+template <int NR>
+__device__ inline void split_mma(const v8bf* __restrict__ op, int k, int lane, float (&xf)[5][8], v4f (&acc)[5][NR]) {
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    union { v2bf h[4]; v8bf v; } hi, lo;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const v2f x = {xf[f][2 * w], xf[f][2 * w + 1]};
+      hi.h[w] = __builtin_convertvector(x, v2bf);
+      const v2f h = __builtin_convertvector(hi.h[w], v2f);
+      lo.h[w] = __builtin_convertvector(x - h, v2bf);
+      xf[f][2 * w] = 0.f;
+      xf[f][2 * w + 1] = 0.f;
+    }
+#pragma unroll
+    for (int rb = 0; rb < NR; ++rb) {
+      const v8bf ah = op[((k * NR + rb) * 2 + 0) * 64 + lane];
+      const v8bf al = op[((k * NR + rb) * 2 + 1) * 64 + lane];
+      acc[f][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, hi.v, acc[f][rb], 0, 0, 0);
+      acc[f][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, lo.v, acc[f][rb], 0, 0, 0);
+      acc[f][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, hi.v, acc[f][rb], 0, 0, 0);
+    }
+  }
+}
+
+// One 16-element tile of one mesh: the whole right-hand side (or fused
+// Runge-Kutta stage) of elements 16 tile .. 16 tile + 15.  `op` is the
+// operator table in the mode's layout, nb / fm the face tables.
+template <int P, int MODE, bool FUSED>
+__device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ s_op, const uint8_t* __restrict__ s_nb,
+                                 const int* __restrict__ s_fm, int64_t tile) {
+  using C = LCfg<P>;
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int64_t Es = A.E * C::NP;
+  const double* __restrict__ q = A.q;
+  const double gm1 = A.gamma - 1.0;
+  {
+    const int64_t e = tile * 16 + n;
+    const bool valid = e < A.E;
+    const int64_t ec = valid ? e : A.E - 1;
+    double gm[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) gm[c] = A.geo[c * A.Epad + ec];
+    int2 cn[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) cn[f] = A.conn[f * A.Epad + ec];
+
+    v4f acc[5][C::NR];
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+      for (int rb = 0; rb < C::NR; ++rb) acc[f][rb] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    if constexpr (MODE == 1) {
+      const float* op = reinterpret_cast<const float*>(s_op);
+#pragma unroll
+      for (int s = 0; s < C::KV; ++s) {
+        const int j = 4 * s + g;
+        double G[3][5];
+        if (j < C::NP) {
+          double qq[5];
+#pragma unroll
+          for (int f = 0; f < 5; ++f) qq[f] = q[f * Es + ec * C::NP + j];
+          contravariant_flux(qq, gm, gm1, G);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int f = 0; f < 5; ++f) G[r][f] = 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int rb = 0; rb < C::NR; ++rb) {
+            const float a = op[((r * C::KV + s) * C::NR + rb) * 64 + lane];
+#pragma unroll
+            for (int f = 0; f < 5; ++f)
+              acc[f][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, static_cast<float>(G[r][f]), acc[f][rb], 0, 0, 0);
+          }
+      }
+#pragma unroll 2
+      for (int s = 0; s < C::KL; ++s) {
+        const int fm = 4 * s + g;
+        const int face = fm / C::NFP;
+        const int mm = fm - face * C::NFP;
+        const int2 c = face == 0 ? cn[0] : face == 1 ? cn[1] : face == 2 ? cn[2] : cn[3];
+        const int own = s_fm[fm];
+        const int jp = s_nb[(face * 24 + c.y) * C::NFP + mm];
+        double qm[5], qp[5], D[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          qm[f] = q[f * Es + ec * C::NP + own];
+          qp[f] = q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
+        }
+        double Nx, Ny, Nz;
+        scaled_normal(face, gm, Nx, Ny, Nz);
+        lf_jump(qm, qp, Nx, Ny, Nz, A.gamma, D);
+#pragma unroll
+        for (int rb = 0; rb < C::NR; ++rb) {
+          const float a = op[((3 * C::KV + s) * C::NR + rb) * 64 + lane];
+#pragma unroll
+          for (int f = 0; f < 5; ++f)
+            acc[f][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, static_cast<float>(D[f]), acc[f][rb], 0, 0, 0);
+        }
+      }
+    } else {
+      const v8bf* op = reinterpret_cast<const v8bf*>(s_op);  // [k][rb][part][64]
+      // One k-step's 8 slots per field are staged in FP32, then split and
+      // sent to the matrix cores.  Volume slot t = 3 s + a holds direction a of
+      // node step s; face slot t holds face-node step t.
+      float xf[5][8];
+#pragma unroll
+      for (int f = 0; f < 5; ++f)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) xf[f][t] = 0.f;
+      double G[3][5];
+#pragma unroll
+      for (int t = 0; t < 3 * C::KV; ++t) {
+        const int s = t / 3, r = t % 3;
+        if (r == 0) {
+          const int j = 4 * s + g;
+          if (j < C::NP) {
+            double qq[5];
+#pragma unroll
+            for (int f = 0; f < 5; ++f) qq[f] = q[f * Es + ec * C::NP + j];
+            contravariant_flux(qq, gm, gm1, G);
+          } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+              for (int f = 0; f < 5; ++f) G[a][f] = 0.0;
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < 5; ++f) xf[f][t % 8] = static_cast<float>(G[r][f]);
+        if (t % 8 == 7 || t == 3 * C::KV - 1) split_mma<C::NR>(op, t / 8, lane, xf, acc);
+      }
+#pragma unroll
+      for (int t = 0; t < C::KL; ++t) {
+        const int fm = 4 * t + g;
+        const int face = fm / C::NFP;
+        const int mm = fm - face * C::NFP;
+        const int2 c = face == 0 ? cn[0] : face == 1 ? cn[1] : face == 2 ? cn[2] : cn[3];
+        const int own = s_fm[fm];
+        const int jp = s_nb[(face * 24 + c.y) * C::NFP + mm];
+        double qm[5], qp[5], D[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          qm[f] = q[f * Es + ec * C::NP + own];
+          qp[f] = q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
+        }
+        double Nx, Ny, Nz;
+        scaled_normal(face, gm, Nx, Ny, Nz);
+        lf_jump(qm, qp, Nx, Ny, Nz, A.gamma, D);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) xf[f][t % 8] = static_cast<float>(D[f]);
+        if (t % 8 == 7 || t == C::KL - 1) split_mma<C::NR>(op, C::VKS + t / 8, lane, xf, acc);
+      }
+    }
+
+    // store: lane (n, g) register v holds row 16 rb + 4 g + v
+    if (valid) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f)
+#pragma unroll
+        for (int rb = 0; rb < C::NR; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * rb + 4 * g + v;
+            if (row < C::NP)
+              emit<FUSED>(f * Es + e * C::NP + row, static_cast<double>(acc[f][rb][v]), A.rhs, A.res, A.qout, q,
+                          A.a, A.b, A.dt);
+          }
+    }
+  }
+}
+
+}  // namespace lowp
+}  // namespace dg

@@ -256,6 +256,18 @@ extern "C" dg_status dg_mesh_create(int order, int64_t n_elem, const double* ele
   if (!build_nbtab(m->ref, m->nbtab)) return cleanup(fail(DG_ERR_MESH, "dg_mesh_create: face-node table failed"));
   std::vector<double> op64;
   build_op64(m->ref, m->lay, op64);
+  // plain FP64 operator, row k of [D_r | D_s | D_t | LIFT] transposed:
+  // opT[k][i] = Op[i][k] (consecutive rows i of one column are contiguous)
+  const int Np = m->Np, KO = 3 * Np + 4 * m->Nfp;
+  std::vector<double> opT(static_cast<size_t>(KO) * Np);
+  for (int i = 0; i < Np; ++i) {
+    for (int j = 0; j < Np; ++j) {
+      opT[static_cast<size_t>(j) * Np + i] = m->ref.Dr[i * Np + j];
+      opT[static_cast<size_t>(Np + j) * Np + i] = m->ref.Ds[i * Np + j];
+      opT[static_cast<size_t>(2 * Np + j) * Np + i] = m->ref.Dt[i * Np + j];
+    }
+    for (int k = 0; k < 4 * m->Nfp; ++k) opT[static_cast<size_t>(3 * Np + k) * Np + i] = m->ref.LIFT[i * 4 * m->Nfp + k];
+  }
   std::vector<float> op32;
   std::vector<uint16_t> opbf;
   build_lowp_tables(m->ref, op32, opbf);
@@ -272,6 +284,7 @@ extern "C" dg_status dg_mesh_create(int order, int64_t n_elem, const double* ele
   dg_status st = up(reinterpret_cast<void**>(&m->d_geo), geo.data(), geo.size() * sizeof(double));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_conn), m->conn_host.data(), m->conn_host.size() * sizeof(int32_t));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_op64), op64.data(), op64.size() * sizeof(double));
+  if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_opT), opT.data(), opT.size() * sizeof(double));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_op32), op32.data(), op32.size() * sizeof(float));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_opbf), opbf.data(), opbf.size() * sizeof(uint16_t));
   if (st == DG_OK) st = up(reinterpret_cast<void**>(&m->d_fmask), m->ref.Fmask.data(), m->ref.Fmask.size() * sizeof(int));
@@ -291,6 +304,7 @@ extern "C" dg_status dg_mesh_destroy(dg_mesh h) {
   hipFree(m->d_geo);
   hipFree(m->d_conn);
   hipFree(m->d_op64);
+  hipFree(m->d_opT);
   hipFree(m->d_op32);
   hipFree(m->d_opbf);
   hipFree(m->d_fmask);

@@ -1,0 +1,332 @@
+// Reacting Navier-Stokes right-hand side with BR1 viscous terms, FP64, gfx950.
+//
+// Two passes per evaluation, both element-local with the reference operators
+// in LDS and one thread per (element, node):
+//
+//  gradient pass   sigma_d(v)_i = sum_a (da/dx_d) (D_a v)_i
+//                                 + sum_f N_{f,d} sum_m LIFT[i, (f, m)] dv_(f,m),
+//                  dv = (v+ - v-) / 2, N_f = Fscale_f n_f (from the metric);
+//                  the element's primitives and face jumps are staged in LDS,
+//                  the thread accumulates D_r v, D_s v, D_t v of all 11
+//                  primitives (each operator entry read once for all of them).
+//  right-hand side rhs_i = -sum_a sum_j D_a[i, j] G_a,j + sum_m LIFT[i, m] Delta_m
+//                  + sources, G_a = total flux along grad a, Delta the face
+//                  jump (Lax-Friedrichs on the inviscid flux, central on the
+//                  viscous one, no penalty).  The fluxes of every volume node
+//                  and the jumps of every face node of the block's elements go
+//                  to LDS; the contractions of the 12 fields are then shared
+//                  out over all threads.
+//
+// FP64 matrix cores and FP64 vector FMAs have the same peak on this chip, so
+// the contractions run on the vector units; the operator entries come from LDS
+// laid out so that consecutive threads (consecutive output rows) read
+// consecutive words.
+#include "internal.hpp"
+#include "ns.hpp"
+#include "ns_point.hpp"
+
+namespace dg {
+namespace {
+
+template <int P>
+struct NsCfg {
+  static constexpr int NP = (P + 1) * (P + 2) * (P + 3) / 6;
+  static constexpr int NFP = (P + 1) * (P + 2) / 2;
+  static constexpr int NFN = 4 * NFP;
+  static constexpr int EPB = 256 / NP;      // elements per block
+  static constexpr int KOP = 3 * NP + NFN;  // operator rows (D_r, D_s, D_t columns, then LIFT columns)
+};
+
+__device__ inline void load_state(const double* __restrict__ q, int64_t Es, int64_t idx, double qq[kNsFields]) {
+#pragma unroll
+  for (int f = 0; f < kNsFields; ++f) qq[f] = q[f * Es + idx];
+}
+
+__device__ inline void load_sigma(const double* __restrict__ sg, int64_t Es, int64_t idx, double s[3 * kNsPrims]) {
+#pragma unroll
+  for (int f = 0; f < 3 * kNsPrims; ++f) s[f] = sg[f * Es + idx];
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
+  using C = NsCfg<P>;
+  __shared__ double s_op[C::KOP * C::NP];
+  __shared__ double s_v[C::EPB][kNsPrims][C::NP];
+  __shared__ double s_d[C::EPB][kNsPrims][C::NFN];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < C::KOP * C::NP; k += blockDim.x) s_op[k] = A.opT[k];
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * C::EPB;
+  const int64_t Es = A.E * C::NP;
+  const int el = tid / C::NP, i = tid - el * C::NP;
+  const bool vol = tid < C::EPB * C::NP;
+  const int64_t e = e0 + el;
+  const bool valid = vol && e < A.E;
+  if (vol) {
+    double v[kNsPrims];
+    if (valid) {
+      double qq[kNsFields];
+      load_state(A.q, Es, e * C::NP + i, qq);
+      ns_primitives(qq, A.T[e * C::NP + i], v);
+    } else {
+#pragma unroll
+      for (int c = 0; c < kNsPrims; ++c) v[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kNsPrims; ++c) s_v[el][c][i] = v[c];
+  }
+  __syncthreads();
+  for (int s = tid; s < C::EPB * C::NFN; s += blockDim.x) {
+    const int fl = s / C::NFN, fm = s - fl * C::NFN;
+    const int64_t ef = e0 + fl;
+    double dv[kNsPrims];
+    if (ef < A.E) {
+      const int face = fm / C::NFP, mm = fm - face * C::NFP;
+      const int2 cn = A.conn[face * A.Epad + ef];
+      const int jp = A.nbtab[(face * 24 + cn.y) * C::NFP + mm];
+      const int own = A.fmask[fm];
+      double qp[kNsFields], vp[kNsPrims];
+      const int64_t ip = static_cast<int64_t>(cn.x) * C::NP + jp;
+      load_state(A.q, Es, ip, qp);
+      ns_primitives(qp, A.T[ip], vp);
+#pragma unroll
+      for (int c = 0; c < kNsPrims; ++c) dv[c] = 0.5 * (vp[c] - s_v[fl][c][own]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < kNsPrims; ++c) dv[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kNsPrims; ++c) s_d[fl][c][fm] = dv[c];
+  }
+  __syncthreads();
+  if (!valid) return;
+  // sig[c][d] first holds D_a v (a = r, s, t), then the physical gradient
+  double sg[kNsPrims][3];
+#pragma unroll
+  for (int c = 0; c < kNsPrims; ++c) sg[c][0] = sg[c][1] = sg[c][2] = 0.0;
+  for (int j = 0; j < C::NP; ++j) {
+    const double dr = s_op[j * C::NP + i];
+    const double ds = s_op[(C::NP + j) * C::NP + i];
+    const double dt = s_op[(2 * C::NP + j) * C::NP + i];
+#pragma unroll
+    for (int c = 0; c < kNsPrims; ++c) {
+      const double vj = s_v[el][c][j];
+      sg[c][0] = fma(dr, vj, sg[c][0]);
+      sg[c][1] = fma(ds, vj, sg[c][1]);
+      sg[c][2] = fma(dt, vj, sg[c][2]);
+    }
+  }
+  double gm[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + e];
+#pragma unroll
+  for (int c = 0; c < kNsPrims; ++c) {
+    const double wr = sg[c][0], ws = sg[c][1], wt = sg[c][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sg[c][d] = gm[d] * wr + gm[3 + d] * ws + gm[6 + d] * wt;
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    double N[3];
+    scaled_normal(f, gm, N[0], N[1], N[2]);
+    double L[kNsPrims];
+#pragma unroll
+    for (int c = 0; c < kNsPrims; ++c) L[c] = 0.0;
+    for (int m = 0; m < C::NFP; ++m) {
+      const double l = s_op[(3 * C::NP + f * C::NFP + m) * C::NP + i];
+#pragma unroll
+      for (int c = 0; c < kNsPrims; ++c) L[c] = fma(l, s_d[el][c][f * C::NFP + m], L[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kNsPrims; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sg[c][d] = fma(N[d], L[c], sg[c][d]);
+  }
+#pragma unroll
+  for (int c = 0; c < kNsPrims; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) A.sigma[(3 * c + d) * Es + e * C::NP + i] = sg[c][d];
+}
+
+// Face jump of one face node (element ef, face node fm):
+//   Delta = 1/2 (N.F(-) - N.F(+)) - 1/2 max(|U_N-| + c- |N|, |U_N+| + c+ |N|) (q- - q+),
+// F the total flux, N = Fscale n.
+template <int P>
+__device__ inline void ns_face_jump(const NsArgs& A, int64_t Es, int64_t ef, int fm, const double gm[9],
+                                    double D[kNsFields]) {
+  using C = NsCfg<P>;
+  const int face = fm / C::NFP, mm = fm - face * C::NFP;
+  const int2 cn = A.conn[face * A.Epad + ef];
+  const int jp = A.nbtab[(face * 24 + cn.y) * C::NFP + mm];
+  const int own = A.fmask[fm];
+  double N[3];
+  scaled_normal(face, gm, N[0], N[1], N[2]);
+  const double Fs = sqrt_pos(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+  const Transport tr{A.mu, A.Pr, A.Sc};
+  double qm[kNsFields], Fm[kNsFields];
+  double Unm, cm;
+  {
+    const int64_t im = ef * C::NP + own;
+    double s[3 * kNsPrims];
+    load_state(A.q, Es, im, qm);
+    load_sigma(A.sigma, Es, im, s);
+    NsNode nd;
+    ns_node(A.th, qm, A.T[im], s, nd);
+    Unm = ns_flux_along(tr, nd, qm, s, N, Fm);
+    cm = nd.c;
+  }
+  const int64_t ip = static_cast<int64_t>(cn.x) * C::NP + jp;
+  double qp[kNsFields], Fp[kNsFields], s[3 * kNsPrims];
+  load_state(A.q, Es, ip, qp);
+  load_sigma(A.sigma, Es, ip, s);
+  NsNode nd;
+  ns_node(A.th, qp, A.T[ip], s, nd);
+  const double Unp = ns_flux_along(tr, nd, qp, s, N, Fp);
+  const double lamFs = fmax(fabs(Unm) + cm * Fs, fabs(Unp) + nd.c * Fs);
+#pragma unroll
+  for (int f = 0; f < kNsFields; ++f) D[f] = 0.5 * (Fm[f] - Fp[f]) - 0.5 * lamFs * (qm[f] - qp[f]);
+}
+
+// Right-hand side: block of EPB_R = 256 / (4 Nfp) elements; thread s < EPB_R 4 Nfp
+// forms the jump of face node s, thread t < EPB_R Np the contravariant fluxes
+// of volume node t, both straight into LDS; then the 12 fields' contractions
+// are split over H = 256 / (EPB_R Np) thread sets of EPB_R Np threads.
+template <int P>
+struct NsRhsCfg {
+  using C = NsCfg<P>;
+  static constexpr int EPB = 256 / C::NFN;
+  static constexpr int NV = EPB * C::NP;  // volume threads
+  static constexpr int H = 256 / NV;      // field sets (1, 2 or 3: divides 12)
+  static constexpr int FH = kNsFields / H;
+};
+
+template <int P, bool FUSED>
+__global__ __launch_bounds__(256) void ns_rhs_kernel(NsArgs A) {
+  using C = NsCfg<P>;
+  using R = NsRhsCfg<P>;
+  static_assert(kNsFields % R::H == 0, "field sets must divide the fields");
+  __shared__ double s_op[C::KOP * C::NP];
+  __shared__ double s_G[R::EPB][kNsFields][3][C::NP];
+  __shared__ double s_D[R::EPB][kNsFields][C::NFN];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < C::KOP * C::NP; k += blockDim.x) s_op[k] = A.opT[k];
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * R::EPB;
+  const int64_t Es = A.E * C::NP;
+  const Transport tr{A.mu, A.Pr, A.Sc};
+
+  if (tid < R::EPB * C::NFN) {  // one face node
+    const int fl = tid / C::NFN, fm = tid - fl * C::NFN;
+    const int64_t ef = e0 + fl;
+    double D[kNsFields];
+    if (ef < A.E) {
+      double gm[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + ef];
+      ns_face_jump<P>(A, Es, ef, fm, gm, D);
+    } else {
+#pragma unroll
+      for (int f = 0; f < kNsFields; ++f) D[f] = 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < kNsFields; ++f) s_D[fl][f][fm] = D[f];
+  }
+  if (tid < R::NV) {  // one volume node
+    const int el = tid / C::NP, i = tid - el * C::NP;
+    const int64_t e = e0 + el;
+    double G[kNsFields];
+    if (e < A.E) {
+      const int64_t idx = e * C::NP + i;
+      double qq[kNsFields], sg[3 * kNsPrims], gm[9];
+      load_state(A.q, Es, idx, qq);
+      load_sigma(A.sigma, Es, idx, sg);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + e];
+      NsNode nd;
+      ns_node(A.th, qq, A.T[idx], sg, nd);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        ns_flux_along(tr, nd, qq, sg, &gm[3 * a], G);
+#pragma unroll
+        for (int f = 0; f < kNsFields; ++f) s_G[el][f][a][i] = G[f];
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int f = 0; f < kNsFields; ++f) s_G[el][f][a][i] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (tid >= R::H * R::NV) return;
+  const int h = tid / R::NV, t = tid - h * R::NV;
+  const int el = t / C::NP, i = t - el * C::NP;
+  const int64_t e = e0 + el;
+  if (e >= A.E) return;
+  const int f0 = h * R::FH;
+  double acc[R::FH];
+#pragma unroll
+  for (int k = 0; k < R::FH; ++k) acc[k] = 0.0;
+  // (partial unrolling: full unrolling hoists hundreds of LDS loads and spills)
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a)
+#pragma unroll 2
+    for (int j = 0; j < C::NP; ++j) {
+      const double d = s_op[(a * C::NP + j) * C::NP + i];
+#pragma unroll
+      for (int k = 0; k < R::FH; ++k) acc[k] = fma(-d, s_G[el][f0 + k][a][j], acc[k]);
+    }
+#pragma unroll 2
+  for (int m = 0; m < C::NFN; ++m) {
+    const double l = s_op[(3 * C::NP + m) * C::NP + i];
+#pragma unroll
+    for (int k = 0; k < R::FH; ++k) acc[k] = fma(l, s_D[el][f0 + k][m], acc[k]);
+  }
+  double w[kNsSpecies];
+  const int64_t idx = e * C::NP + i;
+  if (A.with_sources && f0 + R::FH > 5) {
+    double Cc[kMaxSpecies];
+#pragma unroll
+    for (int k = 0; k < kNsSpecies; ++k) Cc[k] = A.q[(5 + k) * Es + idx] * A.mk.invW[k];
+    node_sources(A.mk, Cc, recip(A.T[idx]), w);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kNsSpecies; ++k) w[k] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < R::FH; ++k) {
+    const int f = f0 + k;
+    const double val = f >= 5 ? acc[k] + w[f - 5] : acc[k];
+    emit<FUSED>(f * Es + idx, val, A.rhs, A.res, A.qout, A.q, A.a, A.b, A.dt);
+  }
+}
+
+template <int P>
+dg_status launch_p(const NsArgs& A, bool grad, bool fused, hipStream_t s) {
+  using C = NsCfg<P>;
+  using R = NsRhsCfg<P>;
+  const dim3 block(256);
+  if (grad)
+    ns_grad_kernel<P><<<dim3(static_cast<unsigned>((A.E + C::EPB - 1) / C::EPB)), block, 0, s>>>(A);
+  else if (fused)
+    ns_rhs_kernel<P, true><<<dim3(static_cast<unsigned>((A.E + R::EPB - 1) / R::EPB)), block, 0, s>>>(A);
+  else
+    ns_rhs_kernel<P, false><<<dim3(static_cast<unsigned>((A.E + R::EPB - 1) / R::EPB)), block, 0, s>>>(A);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+dg_status launch(int p, const NsArgs& A, bool grad, bool fused, hipStream_t s) {
+  switch (p) {
+    case 1: return launch_p<1>(A, grad, fused, s);
+    case 2: return launch_p<2>(A, grad, fused, s);
+    case 3: return launch_p<3>(A, grad, fused, s);
+    case 4: return launch_p<4>(A, grad, fused, s);
+    default: return fail(DG_ERR_ARG, "ns: unsupported order");
+  }
+}
+
+}  // namespace
+
+dg_status launch_ns_gradients(int p, const NsArgs& A, hipStream_t s) { return launch(p, A, true, false, s); }
+dg_status launch_ns_rhs(int p, const NsArgs& A, bool fused, hipStream_t s) { return launch(p, A, false, fused, s); }
+
+}  // namespace dg

@@ -1,0 +1,126 @@
+// C-ABI of the reacting Navier-Stokes right-hand side and its Runge-Kutta step.
+#include <cmath>
+#include <string>
+
+#include "internal.hpp"
+#include "ns.hpp"
+
+namespace dg {
+const ThermoTable& thermo_table(const dg_thermo_s* th);
+int thermo_device(const dg_thermo_s* th);
+const MechTable& mech_table(const dg_mech_s* mk);
+int mech_device(const dg_mech_s* mk);
+}  // namespace dg
+
+using namespace dg;
+
+namespace {
+
+constexpr int kFields = 12, kGrad = 33;
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+bool overlap(const double* a, size_t na, const double* b, size_t nb) { return a < b + nb && b < a + na; }
+
+dg_status check(const char* who, const Mesh& m, const dg_params* prm) {
+  const std::string w(who);
+  if (!prm) return fail(DG_ERR_ARG, w + ": params is NULL");
+  if (prm->model != 1) return fail(DG_ERR_ARG, w + ": model must be 1 (reacting Navier-Stokes)");
+  if (!prm->thermo) return fail(DG_ERR_ARG, w + ": params.thermo is NULL");
+  if (!(prm->mu >= 0.0) || !std::isfinite(prm->mu) || !(prm->Pr > 0.0) || !std::isfinite(prm->Pr) ||
+      !(prm->Sc > 0.0) || !std::isfinite(prm->Sc))
+    return fail(DG_ERR_ARG, w + ": need mu >= 0, Pr > 0 and Sc > 0 (finite)");
+  if (thermo_table(prm->thermo).ns != 7) return fail(DG_ERR_UNSUPPORTED, w + ": the reacting path needs 7 species");
+  if (thermo_device(prm->thermo) != m.device) return fail(DG_ERR_ARG, w + ": thermo table lives on another device");
+  if (prm->mech) {
+    if (mech_table(prm->mech).ns != 7) return fail(DG_ERR_UNSUPPORTED, w + ": the reacting path needs 7 species");
+    if (mech_device(prm->mech) != m.device) return fail(DG_ERR_ARG, w + ": mechanism lives on another device");
+  }
+  return DG_OK;
+}
+
+NsArgs make_args(const Mesh& m, const dg_params* prm) {
+  NsArgs A{};
+  A.geo = m.d_geo;
+  A.conn = m.d_conn;
+  A.opT = m.d_opT;
+  A.fmask = m.d_fmask;
+  A.nbtab = m.d_nbtab;
+  A.E = m.E;
+  A.Epad = m.Epad;
+  A.mu = prm->mu;
+  A.Pr = prm->Pr;
+  A.Sc = prm->Sc;
+  A.th = thermo_table(prm->thermo);
+  A.with_sources = prm->mech ? 1 : 0;
+  if (prm->mech) A.mk = mech_table(prm->mech);
+  return A;
+}
+
+}  // namespace
+
+extern "C" dg_status dg_ns_rhs(dg_mesh h, const dg_params* prm, const double* q, const double* T, double* sigma,
+                               double* rhs, hipStream_t stream) {
+  if (!h) return fail(DG_ERR_ARG, "dg_ns_rhs: null mesh");
+  const Mesh& m = *reinterpret_cast<const Mesh*>(h);
+  dg_status st = check("dg_ns_rhs", m, prm);
+  if (st != DG_OK) return st;
+  if (!q || !T || !sigma || !rhs || !aligned8(q) || !aligned8(T) || !aligned8(sigma) || !aligned8(rhs))
+    return fail(DG_ERR_ARG, "dg_ns_rhs: null or misaligned pointer");
+  const size_t n = static_cast<size_t>(m.E) * m.Np;
+  if (overlap(rhs, kFields * n, q, kFields * n) || overlap(rhs, kFields * n, T, n) ||
+      overlap(rhs, kFields * n, sigma, kGrad * n) || overlap(sigma, kGrad * n, q, kFields * n) ||
+      overlap(sigma, kGrad * n, T, n))
+    return fail(DG_ERR_ARG, "dg_ns_rhs: outputs overlap inputs");
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_ns_rhs: hipSetDevice failed");
+  NsArgs A = make_args(m, prm);
+  A.q = q;
+  A.T = T;
+  A.sigma = sigma;
+  A.rhs = rhs;
+  st = launch_ns_gradients(m.p, A, stream);
+  if (st != DG_OK) return st;
+  return launch_ns_rhs(m.p, A, false, stream);
+}
+
+extern "C" dg_status dg_ns_rk_step(dg_mesh h, const dg_params* prm, double* q, double* T, double* work, double dt,
+                                   double tol, int max_iter, hipStream_t stream) {
+  if (!h) return fail(DG_ERR_ARG, "dg_ns_rk_step: null mesh");
+  const Mesh& m = *reinterpret_cast<const Mesh*>(h);
+  dg_status st = check("dg_ns_rk_step", m, prm);
+  if (st != DG_OK) return st;
+  if (!q || !T || !work || !aligned8(q) || !aligned8(T) || !aligned8(work))
+    return fail(DG_ERR_ARG, "dg_ns_rk_step: null or misaligned pointer");
+  if (!std::isfinite(dt)) return fail(DG_ERR_ARG, "dg_ns_rk_step: dt must be finite");
+  if (!(tol > 0.0) || max_iter < 1) return fail(DG_ERR_ARG, "dg_ns_rk_step: need tol > 0 and max_iter >= 1");
+  const size_t n = static_cast<size_t>(m.E) * m.Np;
+  if (overlap(work, 58 * n, q, kFields * n) || overlap(work, 58 * n, T, n) || overlap(q, kFields * n, T, n))
+    return fail(DG_ERR_ARG, "dg_ns_rk_step: q, T and work must not overlap");
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_ns_rk_step: hipSetDevice failed");
+  double* res = work;
+  double* buf[2] = {q, work + kFields * n};
+  double* sigma = work + 2 * kFields * n;
+  int32_t* iters = reinterpret_cast<int32_t*>(work + (2 * kFields + kGrad) * n);
+  const ThermoTable& th = thermo_table(prm->thermo);
+  NsArgs A = make_args(m, prm);
+  A.sigma = sigma;
+  A.T = T;
+  A.res = res;
+  A.dt = dt;
+  for (int s = 0; s < 5; ++s) {
+    A.q = buf[s & 1];
+    A.qout = buf[(s + 1) & 1];
+    A.a = kLsrkA[s];
+    A.b = kLsrkB[s];
+    st = launch_temperature(th, static_cast<int64_t>(n), A.q, T, 1000.0, T, iters, tol, max_iter, stream);
+    if (st != DG_OK) return st;
+    st = launch_ns_gradients(m.p, A, stream);
+    if (st != DG_OK) return st;
+    st = launch_ns_rhs(m.p, A, true, stream);
+    if (st != DG_OK) return st;
+  }
+  DG_HIP(hipMemcpyAsync(q, buf[1], kFields * n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  return DG_OK;
+}

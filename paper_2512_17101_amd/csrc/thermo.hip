@@ -59,21 +59,10 @@ __global__ __launch_bounds__(256) void sources_kernel(MechTable mk, int64_t n, c
                                                       const double* __restrict__ T, double* __restrict__ omega) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double C[kMaxSpecies];
+    double C[kMaxSpecies], w[kMaxSpecies];
     for (int k = 0; k < mk.ns; ++k) C[k] = q[(5 + k) * n + i] * mk.invW[k];
-    const double iT = 1.0 / T[i];
-    double r[kMaxReactions];
-    for (int j = 0; j < mk.nr; ++j) {
-      double rj = mk.A[j] * exp(-mk.EaR[j] * iT);
-      for (int k = 0; k < mk.ns; ++k)
-        for (int m = 0; m < mk.nu_r[j][k]; ++m) rj *= C[k];
-      r[j] = rj;
-    }
-    for (int k = 0; k < mk.ns; ++k) {
-      double w = 0.0;
-      for (int j = 0; j < mk.nr; ++j) w += mk.Wnet[k][j] * r[j];
-      omega[k * n + i] = w;
-    }
+    node_sources(mk, C, 1.0 / T[i], w);
+    for (int k = 0; k < mk.ns; ++k) omega[k * n + i] = w[k];
   }
 }
 

@@ -30,6 +30,24 @@ struct MechTable {
   double Wnet[kMaxSpecies][kMaxReactions];  // W_k (nu''_kj - nu'_kj)
 };
 
+// Species sources of one node from its molar concentrations C_k = rho Y_k / W_k
+// and 1 / T: k_j = A_j exp(-Ea_j / (R_u T)), r_j = k_j prod_k C_k^{nu'_kj},
+// omega_k = sum_j W_k (nu''_kj - nu'_kj) r_j.
+__device__ inline void node_sources(const MechTable& mk, const double* C, double iT, double* omega) {
+  double r[kMaxReactions];
+  for (int j = 0; j < mk.nr; ++j) {
+    double rj = mk.A[j] * exp(-mk.EaR[j] * iT);
+    for (int k = 0; k < mk.ns; ++k)
+      for (int m = 0; m < mk.nu_r[j][k]; ++m) rj *= C[k];
+    r[j] = rj;
+  }
+  for (int k = 0; k < mk.ns; ++k) {
+    double w = 0.0;
+    for (int j = 0; j < mk.nr; ++j) w += mk.Wnet[k][j] * r[j];
+    omega[k] = w;
+  }
+}
+
 dg_status launch_temperature(const ThermoTable& th, int64_t n, const double* q, const double* Tguess,
                              double Tdefault, double* Tout, int32_t* iters, double tol, int max_iter, hipStream_t s);
 dg_status launch_sources(const MechTable& mk, int64_t n, const double* q, const double* T, double* omega,

@@ -136,5 +136,7 @@ extern "C" dg_status dg_sources(dg_mech mech, int64_t n, const double* q, const 
 
 namespace dg {
 const ThermoTable& thermo_table(const dg_thermo_s* th) { return th->t; }
+const MechTable& mech_table(const dg_mech_s* mk) { return mk->m; }
+int mech_device(const dg_mech_s* mk) { return mk->device; }
 int thermo_device(const dg_thermo_s* th) { return th->device; }
 }  // namespace dg

@@ -26,7 +26,9 @@ EXPORTS = ("dg_reference_operators", "dg_mesh_create", "dg_mesh_info", "dg_mesh_
            "dg_mech_create", "dg_mech_destroy", "dg_temperature", "dg_sources", "dg_mlp_create", "dg_mlp_destroy",
            "dg_mlp_set_params", "dg_mlp_get_params", "dg_mlp_set_normalization", "dg_mlp_get_normalization",
            "dg_mlp_fit_normalization", "dg_mlp_loss_grad", "dg_mlp_train_step", "dg_mlp_predict",
-           "dg_temperature_learned", "dg_last_error")
+           "dg_temperature_learned", "dg_batch_create", "dg_batch_destroy", "dg_batch_bind",
+           "dg_batch_set_config", "dg_batch_get_config", "dg_batch_rk_step", "dg_batch_info", "dg_batch_autotune",
+           "dg_ns_rhs", "dg_ns_rk_step", "dg_last_error")
 
 
 class DGError(RuntimeError):
@@ -36,7 +38,18 @@ class DGError(RuntimeError):
 
 
 class _Params(ctypes.Structure):
-    _fields_ = [("model", ctypes.c_int), ("gamma", ctypes.c_double)]
+    _fields_ = [("model", ctypes.c_int), ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("Sc", ctypes.c_double), ("thermo", ctypes.c_void_p),
+                ("mech", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    """dg_batch_config: launch shape of the batched stage kernel."""
+    _fields_ = [("waves_per_block", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("order", ctypes.c_int),
+                ("xcd_chunks", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib_handle = None
@@ -80,6 +93,17 @@ def lib():
         L.dg_mlp_predict.argtypes = [_c_p, _i64, _i64, _c_p, _c_p, _c_p]
         L.dg_temperature_learned.argtypes = [_c_p, _c_p, _i64, _c_p, _dbl, _c_p, _c_p, _dbl, ctypes.c_int,
                                              ctypes.c_int, _c_p, _c_p]
+        L.dg_batch_create.argtypes = [_c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_c_p)]
+        L.dg_batch_destroy.argtypes = [_c_p]
+        L.dg_batch_bind.argtypes = [_c_p, _c_p, _c_p, _c_p]
+        L.dg_batch_set_config.argtypes = [_c_p, ctypes.POINTER(BatchConfig)]
+        L.dg_batch_get_config.argtypes = [_c_p, ctypes.POINTER(BatchConfig)]
+        L.dg_batch_rk_step.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_int, _c_p]
+        L.dg_batch_info.argtypes = [_c_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int)]
+        L.dg_batch_autotune.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_char_p, ctypes.c_int,
+                                        ctypes.POINTER(BatchConfig), ctypes.POINTER(_dbl), _c_p]
+        L.dg_ns_rhs.argtypes = [_c_p, ctypes.POINTER(_Params), _c_p, _c_p, _c_p, _c_p, _c_p]
+        L.dg_ns_rk_step.argtypes = [_c_p, ctypes.POINTER(_Params), _c_p, _c_p, _c_p, _dbl, _dbl, ctypes.c_int, _c_p]
         for name in EXPORTS:
             if name != "dg_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -173,7 +197,42 @@ class Mesh:
 
 
 def _params(gamma: float, model: int = 0):
-    return _Params(model, gamma)
+    return _Params(model, gamma, 0.0, 0.0, 0.0, None, None)
+
+
+MU, PR, SC = 1.8e-5, 0.71, 0.71
+NS_WORK_PER_NODE = 58  # doubles of dg_ns_rk_step scratch per node
+
+
+def _ns_params(thermo, mech, mu, Pr, Sc):
+    return _Params(1, 0.0, float(mu), float(Pr), float(Sc), thermo.handle.value,
+                   None if mech is None else mech.handle.value)
+
+
+def ns_rhs(mesh: Mesh, thermo, q, T, sigma, out, mech=None, mu: float = MU, Pr: float = PR, Sc: float = SC,
+           stream=None):
+    """Reacting Navier-Stokes RHS: q [12, E, Np], T [E, Np] -> sigma [33, E, Np]
+    (lifted gradients) and out [12, E, Np]; mech=None leaves out the sources."""
+    n = mesh.E * mesh.Np
+    if q.numel() != 12 * n or T.numel() != n or sigma.numel() != 33 * n or out.numel() != 12 * n:
+        raise ValueError("q/out must be [12, E, Np], T [E, Np], sigma [33, E, Np]")
+    prm = _ns_params(thermo, mech, mu, Pr, Sc)
+    _check(lib().dg_ns_rhs(mesh.handle, ctypes.byref(prm), _dev_ptr(q), _dev_ptr(T), _dev_ptr(sigma), _dev_ptr(out),
+                           _stream(stream)))
+    return out
+
+
+def ns_rk_step(mesh: Mesh, thermo, q, T, work, dt: float, mech=None, mu: float = MU, Pr: float = PR,
+               Sc: float = SC, tol: float = 1e-10, max_iter: int = 50, stream=None):
+    """One LSRK(5,4) step of the reacting NS system; q and T updated in place;
+    work holds >= 58 E Np doubles."""
+    n = mesh.E * mesh.Np
+    if q.numel() != 12 * n or T.numel() != n or work.numel() < NS_WORK_PER_NODE * n:
+        raise ValueError("q must be [12, E, Np], T [E, Np], work >= 58 E Np doubles")
+    prm = _ns_params(thermo, mech, mu, Pr, Sc)
+    _check(lib().dg_ns_rk_step(mesh.handle, ctypes.byref(prm), _dev_ptr(q), _dev_ptr(T), _dev_ptr(work), float(dt),
+                               float(tol), int(max_iter), _stream(stream)))
+    return q
 
 
 def rhs(mesh: Mesh, q, out, precision: str = "fp64", gamma: float = 1.4, stream=None):
@@ -359,3 +418,73 @@ def temperature_learned(thermo: Thermo, mlp: MLP, q, T_out, iters, T_default: fl
     _check(lib().dg_temperature_learned(thermo.handle, mlp.handle, n, _dev_ptr(q), float(T_default),
                                         _dev_ptr(T_out), _dev_ptr(iters, "int32"), float(tol), int(max_iter),
                                         int(learned_max_iter), fb, _stream(stream)))
+
+
+class Batch:
+    """Owning wrapper of a dg_batch handle: many meshes stepped with one
+    launch per Runge-Kutta stage.  The bound tensors are kept referenced here
+    so they outlive the handle's use of them."""
+
+    def __init__(self, meshes, precision: str = "fp32"):
+        self.meshes = list(meshes)
+        arr = (_c_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        h = ctypes.c_void_p()
+        _check(lib().dg_batch_create(arr, len(self.meshes), PRECISIONS[precision], ctypes.byref(h)))
+        self._h = h
+        self._bound = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def bind(self, qs, works, dt):
+        """qs[i]: [5, E_i, Np_i] float64 device tensors, works[i] >= 2 state
+        arrays each, dt: float64 device tensor [n]."""
+        n = len(self.meshes)
+        if len(qs) != n or len(works) != n or dt.numel() != n:
+            raise ValueError("one state, one work buffer and one dt per mesh")
+        for m, q, w in zip(self.meshes, qs, works):
+            if q.numel() != 5 * m.E * m.Np or w.numel() < 2 * q.numel():
+                raise ValueError("state or work buffer of the wrong size")
+        qa = (_c_p * n)(*[_dev_ptr(q).value for q in qs])
+        wa = (_c_p * n)(*[_dev_ptr(w).value for w in works])
+        _check(lib().dg_batch_bind(self._h, qa, wa, _dev_ptr(dt)))
+        self._bound = (list(qs), list(works), dt)
+
+    def set_config(self, waves_per_block=4, blocks_per_cu=2, order=0, xcd_chunks=0):
+        c = BatchConfig(waves_per_block, blocks_per_cu, order, xcd_chunks)
+        _check(lib().dg_batch_set_config(self._h, ctypes.byref(c)))
+
+    def get_config(self) -> dict:
+        c = BatchConfig()
+        _check(lib().dg_batch_get_config(self._h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def rk_step(self, gamma: float = 1.4, use_graph: bool = True, stream=None):
+        prm = _params(gamma)
+        _check(lib().dg_batch_rk_step(self._h, ctypes.byref(prm), int(bool(use_graph)), _stream(stream)))
+
+    def info(self) -> dict:
+        ni, ne, nk = _i64(), _i64(), ctypes.c_int()
+        _check(lib().dg_batch_info(self._h, ctypes.byref(ni), ctypes.byref(ne), ctypes.byref(nk)))
+        return dict(n_items=ni.value, n_elem=ne.value, graph_kernel_nodes=nk.value)
+
+    def autotune(self, gamma: float = 1.4, cache_path=None, trials: int = 3, stream=None):
+        """Tune the launch shape; returns (config dict, ms per step or -1 from cache)."""
+        prm = _params(gamma)
+        c, ms = BatchConfig(), _dbl()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(lib().dg_batch_autotune(self._h, ctypes.byref(prm), path, int(trials), ctypes.byref(c),
+                                       ctypes.byref(ms), _stream(stream)))
+        return c.as_dict(), ms.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dg_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

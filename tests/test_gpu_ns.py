@@ -1,0 +1,174 @@
+"""GPU reacting Navier-Stokes right-hand side (BR1 viscous terms) against the
+oracle, through the C ABI.
+
+Bar (FP64): every lifted gradient and right-hand-side entry within 1e-12 of
+the magnitude of the terms summed into it (Higham's dot-product scale,
+per field; the chemical source's magnitude is added for species), on
+ragged meshes of every order; Runge-Kutta steps with the GPU's own
+temperature Newton track the oracle's steps."""
+import numpy as np
+import pytest
+
+from oracle import lsrk as olsrk, mesh as om, ns, reference_element as ore, thermo as ot
+from paper_2512_17101_amd import dg, workload as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TH = wl.synthetic_thermo(3003)
+MECH = wl.synthetic_mechanism(3004)
+L = 0.01
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _case(p, dims, seed=1003, state_seed=3005, jitter=0.03):
+    xyz, vid = wl.kuhn_mesh(dims, (L * dims[0] / max(dims), L * dims[1] / max(dims), L * dims[2] / max(dims)),
+                            jitter, seed)
+    ops = ore.operators(p)
+    geo = om.geometry(xyz)
+    conn = om.connectivity(vid, p)
+    X = om.node_coordinates(xyz, ops["rst"])
+    q = wl.reacting_state(X.reshape(-1, 3), seed=state_seed, L=L, n_cells=max(dims)).reshape((12,) + X.shape[:2])
+    T, it = ns.temperature(q, TH)
+    assert np.all(it > 0)
+    return xyz, vid, ops, geo, conn, np.ascontiguousarray(q), T
+
+
+def _sigma_magnitude(ops, geo, conn, v):
+    """sum_a |da/dx_d| (|D_a| |v|) + |LIFT| (|Fscale n_d| |v+ - v-| / 2): the
+    scale of the rounding error of each lifted-gradient entry."""
+    Nfp = ops["Nfp"]
+    fm = ops["Fmask"].reshape(-1)
+    av = np.abs(v)
+    Dv = [av @ np.abs(D).T for D in (ops["Dr"], ops["Ds"], ops["Dt"])]
+    jump = 0.5 * np.abs(v[:, conn["mapP_elem"], conn["mapP_node"]] - v[:, :, fm])
+    n = np.repeat(geo["normals"], Nfp, axis=1)
+    Fs = np.repeat(geo["Fscale"], Nfp, axis=1)
+    out = np.empty((3,) + v.shape)
+    for d in range(3):
+        out[d] = sum(np.abs(geo["rst_x"][None, :, a, d, None]) * Dv[a] for a in range(3))
+        out[d] += (Fs * np.abs(n[..., d]) * jump) @ np.abs(ops["LIFT"]).T
+    return out
+
+
+def _run(mesh, q_np, T_np, mech, mu):
+    dev = _dev()
+    q = torch.from_numpy(q_np).to(dev)
+    T = torch.from_numpy(np.ascontiguousarray(T_np)).to(dev)
+    sig = torch.empty((33,) + tuple(T.shape), dtype=torch.float64, device=dev)
+    out = torch.empty_like(q)
+    th = dg.Thermo(TH["W"], TH["a"])
+    mk = dg.Mechanism(th, MECH["A"], MECH["Ea"], MECH["nu_r"], MECH["nu_p"]) if mech else None
+    dg.ns_rhs(mesh, th, q, T, sig, out, mech=mk, mu=mu)
+    torch.cuda.synchronize()
+    return sig.cpu().numpy(), out.cpu().numpy()
+
+
+def _check(ops, geo, conn, q, T, sig_gpu, rhs_gpu, mech, mu, label):
+    v = ns.primitive_fields(q, T)
+    sig_ref = ns.gradients(ops, geo, conn, v)
+    # device layout: field 3 c + d  ->  reference layout [d][c]
+    sg = np.swapaxes(sig_gpu.reshape((11, 3) + T.shape), 0, 1)  # [33] = [c][d] -> [d][c]
+    smag = _sigma_magnitude(ops, geo, conn, v)
+    es = np.abs(sg - sig_ref) / smag.max(axis=(2, 3), keepdims=True)
+    r_ref, _, mag = ns.rhs(ops, geo, conn, q, T, TH, MECH if mech else None, mu=mu, sigma=sig_ref, split=True)
+    scale = mag.max(axis=(1, 2))
+    if mech:
+        w = ot.sources(q[0], T, q[5:] / q[0], TH, MECH)
+        scale[5:] += np.abs(w).max(axis=(1, 2))
+    er = np.abs(rhs_gpu - r_ref).max(axis=(1, 2)) / scale
+    print(f"{label}: max sigma err / scale {es.max():.2e}, rhs err / scale per field {np.array2string(er, precision=1)}")
+    assert np.all(np.isfinite(rhs_gpu))
+    assert es.max() <= 1e-12
+    assert np.all(er <= 1e-12)
+
+
+@pytest.mark.parametrize("p,dims", [(1, (3, 3, 4)), (2, (3, 4, 3)), (3, (3, 3, 5)), (4, (3, 3, 3))])
+def test_ns_rhs_matches_oracle(p, dims):
+    xyz, vid, ops, geo, conn, q, T = _case(p, dims)
+    mesh = dg.Mesh(p, xyz, vid)
+    for mech, mu in ((True, ns.MU), (False, 50.0 * ns.MU)):
+        sig, rhs = _run(mesh, q, T, mech, mu)
+        _check(ops, geo, conn, q, T, sig, rhs, mech, mu, f"p={p} E={mesh.E} mech={mech} mu={mu:.1e}")
+
+
+def test_ns_rhs_multi_block_p3():
+    xyz, vid, ops, geo, conn, q, T = _case(3, (6, 6, 6), seed=1004, state_seed=3007)
+    mesh = dg.Mesh(3, xyz, vid)
+    sig, rhs = _run(mesh, q, T, True, ns.MU)
+    _check(ops, geo, conn, q, T, sig, rhs, True, ns.MU, f"p=3 E={mesh.E}")
+    sig2, rhs2 = _run(mesh, q, T, True, ns.MU)
+    assert np.array_equal(rhs, rhs2) and np.array_equal(sig, sig2)
+
+
+def test_ns_uniform_state_gives_zero():
+    xyz, vid, ops, geo, conn, q, T = _case(2, (3, 3, 3))
+    qu = np.ascontiguousarray(np.broadcast_to(q[:, :1, :1], q.shape))
+    Tu, _ = ns.temperature(qu, TH)
+    mesh = dg.Mesh(2, xyz, vid)
+    sig, rhs = _run(mesh, qu, Tu, False, 1.0)
+    _, _, mag = ns.rhs(ops, geo, conn, qu, Tu, TH, None, mu=1.0, split=True)
+    assert np.all(np.abs(rhs).max(axis=(1, 2)) <= 1e-11 * mag.max(axis=(1, 2)))
+    v = ns.primitive_fields(qu, Tu)
+    assert np.abs(sig).max() <= 1e-11 * np.abs(v).max() * geo["Fscale"].max()
+
+
+def test_ns_rk_steps_track_oracle():
+    dev = _dev()
+    p = 2
+    xyz, vid, ops, geo, conn, q0, T0 = _case(p, (3, 3, 3), state_seed=3006)
+    mesh = dg.Mesh(p, xyz, vid)
+    dt = 2e-8
+    mu = 10.0 * ns.MU
+
+    def f(qq, tt):
+        T, it = ns.temperature(qq, TH)
+        assert np.all(it > 0)
+        return ns.rhs(ops, geo, conn, qq, T, TH, MECH, mu=mu)
+
+    qe = q0.copy()
+    for s in range(3):
+        qe, _ = olsrk.lsrk_step(f, qe, s * dt, dt)
+    th = dg.Thermo(TH["W"], TH["a"])
+    mk = dg.Mechanism(th, MECH["A"], MECH["Ea"], MECH["nu_r"], MECH["nu_p"])
+    q = torch.from_numpy(q0).to(dev)
+    T = torch.full(T0.shape, 1000.0, dtype=torch.float64, device=dev)
+    work = torch.empty(dg.NS_WORK_PER_NODE * mesh.E * mesh.Np, dtype=torch.float64, device=dev)
+    for s in range(3):
+        dg.ns_rk_step(mesh, th, q, T, work, dt, mech=mk, mu=mu)
+    torch.cuda.synchronize()
+    got = q.cpu().numpy()
+    n = mesh.E * mesh.Np
+    iters = work[57 * n:58 * n].view(torch.int32)[:n].cpu().numpy()
+    assert np.all(iters >= 1)  # last stage's Newton converged everywhere
+    scale = np.abs(qe).max(axis=(1, 2))
+    scale[1:4] = scale[1:4].max()
+    err = np.abs(got - qe).max(axis=(1, 2)) / scale
+    change = np.abs(qe - q0).max(axis=(1, 2)) / scale
+    print("3 NS steps: per-field rel diff vs oracle", err, "relative change", change)
+    assert np.all(err <= 1e-11)
+
+
+def test_ns_error_paths():
+    dev = _dev()
+    xyz, vid, ops, geo, conn, q, T = _case(1, (3, 3, 3))
+    mesh = dg.Mesh(1, xyz, vid)
+    th = dg.Thermo(TH["W"], TH["a"])
+    qt = torch.from_numpy(q).to(dev)
+    Tt = torch.from_numpy(np.ascontiguousarray(T)).to(dev)
+    sig = torch.empty((33,) + T.shape, dtype=torch.float64, device=dev)
+    out = torch.empty_like(qt)
+    with pytest.raises(dg.DGError, match="mu >= 0"):
+        dg.ns_rhs(mesh, th, qt, Tt, sig, out, mu=-1.0)
+    with pytest.raises(dg.DGError, match="overlap"):
+        dg.ns_rhs(mesh, th, qt, Tt, sig, qt)
+    prm = dg._Params(0, 1.4, 0.0, 0.0, 0.0, None, None)
+    import ctypes
+    st = dg.lib().dg_ns_rhs(mesh.handle, ctypes.byref(prm), dg._dev_ptr(qt), dg._dev_ptr(Tt), dg._dev_ptr(sig),
+                            dg._dev_ptr(out), dg._stream(None))
+    assert st == 1 and b"model must be 1" in dg.lib().dg_last_error()
