@@ -203,6 +203,128 @@ def batched_leg(dg, wl, dev, stream, steps):
     return out
 
 
+def _time_ms(stream, fn, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def reacting_leg(dg, wl, dev, stream, steps):
+    """Reacting Navier-Stokes with BR1 viscous terms: periodic [0, 1 cm]^3,
+    32^3 cubes x 6 = 196,608 tets, 3 % jitter, p = 3, 7 species, seeded
+    300-2200 K fronts.  Times the temperature Newton (plain 1000 K start),
+    the gradient + right-hand-side passes and one fused LSRK step."""
+    import torch
+    n, p = 32, 3
+    xyz, vid = wl.kuhn_box_mesh(n, 0.01, 0.03, 1003)
+    mesh = dg.Mesh(p, xyz, vid, 0)
+    X = mesh.nodes().reshape(-1, 3)
+    q_np = wl.reacting_state(X, seed=3005, L=0.01, n_cells=n).reshape(12, mesh.E, mesh.Np)
+    TH, MECH = wl.synthetic_thermo(3003), wl.synthetic_mechanism(3004)
+    th = dg.Thermo(TH["W"], TH["a"])
+    mk = dg.Mechanism(th, MECH["A"], MECH["Ea"], MECH["nu_r"], MECH["nu_p"])
+    q = torch.from_numpy(np.ascontiguousarray(q_np)).to(dev)
+    nn = mesh.E * mesh.Np
+    T = torch.empty((mesh.E, mesh.Np), dtype=torch.float64, device=dev)
+    it = torch.empty((mesh.E, mesh.Np), dtype=torch.int32, device=dev)
+    sig = torch.empty((33, mesh.E, mesh.Np), dtype=torch.float64, device=dev)
+    out = torch.empty_like(q)
+    with torch.cuda.stream(stream):
+        dg.temperature(th, q, T, it, stream=stream)
+        dg.ns_rhs(mesh, th, q, T, sig, out, mech=mk, stream=stream)
+        stream.synchronize()
+        ms_T = _time_ms(stream, lambda: dg.temperature(th, q, T, it, stream=stream), steps)
+        ms_rhs = _time_ms(stream, lambda: dg.ns_rhs(mesh, th, q, T, sig, out, mech=mk, stream=stream), steps)
+        work = torch.empty(dg.NS_WORK_PER_NODE * nn, dtype=torch.float64, device=dev)
+        qs, Ts = q.clone(), T.clone()
+        dg.ns_rk_step(mesh, th, qs, Ts, work, 1e-9, mech=mk, stream=stream)
+        stream.synchronize()
+        ms_rk = _time_ms(stream, lambda: dg.ns_rk_step(mesh, th, qs, Ts, work, 1e-9, mech=mk, stream=stream),
+                         max(2, steps // 5))
+    iters = it.cpu().numpy()
+    finite = bool(torch.isfinite(out).all()) and bool(torch.isfinite(qs).all())
+    dof_f = nn * 12
+    rec = {"workload": "reacting_ns_p3_32cubed", "elements": mesh.E, "order": p, "fields": 12, "species": 7,
+           "mu": dg.MU, "Pr": dg.PR, "Sc": dg.SC,
+           "ns_rhs_ms": round(ms_rhs, 4), "value": round(dof_f / (ms_rhs * 1e-3) / 1e9, 3),
+           "unit": "GDOF·fields/s (gradient + right-hand side, sources included)",
+           "temperature_ms": round(ms_T, 4), "newton_mean_iters_from_1000K": round(float(iters.mean()), 3),
+           "newton_failures": int((iters < 0).sum()), "rk_step_ms": round(ms_rk, 4), "finite": finite}
+    return rec
+
+
+def learned_leg(dg, wl, dev, stream, X48):
+    """Learned temperature guess: the 9-64-64-64-1 network trained on the GPU
+    (BF16 matrix cores, FP32 masters, Adam) on 2M node states of reacting
+    fields on the 32^3 p=3 mesh (other seeds), then evaluated inside Newton on
+    the 48^3 p=3 mesh's 13.27M nodes carrying reacting fields (coordinates
+    scaled to the 1 cm box).  Plain Newton from 1000 K is the reference."""
+    import torch
+    TH = wl.synthetic_thermo(3003)
+    th = dg.Thermo(TH["W"], TH["a"])
+    # training states
+    xyz, vid = wl.kuhn_box_mesh(32, 0.01, 0.03, 1003)
+    m32 = dg.Mesh(3, xyz, vid, 0)
+    X32 = m32.nodes().reshape(-1, 3)
+    qs = [torch.from_numpy(wl.reacting_state(X32, seed=sd, L=0.01, n_cells=32)).to(dev) for sd in (3105, 3205)]
+    qtr = torch.cat(qs, dim=1).contiguous()
+    del qs
+    ntr = qtr.shape[1]
+    Ttr = torch.empty(ntr, dtype=torch.float64, device=dev)
+    itr = torch.empty(ntr, dtype=torch.int32, device=dev)
+    dg.temperature(th, qtr, Ttr, itr)
+    gen = torch.Generator().manual_seed(4003)
+    pick = torch.randperm(ntr, generator=gen)[:2_000_000].to(dev)
+    net = dg.MLP(seed=4002)
+    net.fit_normalization(qtr, pick, Ttr)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    batch, epochs = 4096, 4
+    nb = pick.numel() // batch
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for ep in range(epochs):
+            perm = pick[torch.randperm(pick.numel(), generator=gen).to(dev)]
+            for b in range(nb):
+                net.train_step(qtr, perm[b * batch:(b + 1) * batch], Ttr, lr=1e-3, loss=loss, stream=stream)
+        stream.synchronize()
+    train_s = time.perf_counter() - t0
+    del qtr, Ttr, itr, pick
+    # evaluation on the 48^3 mesh's nodes
+    q = torch.from_numpy(wl.reacting_state(X48.reshape(-1, 3) * 1e-3, seed=3005, L=0.01, n_cells=48)).to(dev)
+    n = q.shape[1]
+    Tp, ip = torch.empty(n, dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.int32, device=dev)
+    Tl, il = torch.empty_like(Tp), torch.empty_like(ip)
+    fb = torch.zeros(1, dtype=torch.int32, device=dev)
+    with torch.cuda.stream(stream):
+        dg.temperature(th, q, Tp, ip, stream=stream)
+        dg.temperature_learned(th, net, q, Tl, il, fallback_count=fb, stream=stream)
+        stream.synchronize()
+        ms_p = _time_ms(stream, lambda: dg.temperature(th, q, Tp, ip, stream=stream), 10)
+        fb.zero_()
+        ms_l = _time_ms(stream, lambda: dg.temperature_learned(th, net, q, Tl, il, fallback_count=fb,
+                                                               stream=stream), 10)
+    fallbacks = fb.item() / 10  # counted over the 10 timed calls
+    Tpred = torch.empty_like(Tp)
+    net.predict(q, Tpred)
+    torch.cuda.synchronize()
+    ipn, iln = ip.cpu().numpy(), il.cpu().numpy()
+    return {"workload": "reacting_fields_on_48cubed_p3_nodes", "nodes": n,
+            "train": {"states": 2_000_000, "batch": batch, "epochs": epochs, "adam_steps": epochs * nb,
+                      "final_batch_loss": round(loss.item(), 6), "seconds": round(train_s, 2)},
+            "plain": {"ms": round(ms_p, 4), "mean_iters": round(float(ipn.mean()), 3),
+                      "failures": int((ipn < 0).sum())},
+            "learned": {"ms": round(ms_l, 4), "mean_iters": round(float(iln.mean()), 3),
+                        "fallbacks": fallbacks, "fallback_rate": fallbacks / n,
+                        "max_abs_dT_vs_plain_K": float((Tl - Tp).abs().max().item()),
+                        "guess_rms_error_K": float(((Tpred - Tp) ** 2).mean().sqrt().item())},
+            "speedup_vs_plain": round(ms_p / ms_l, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +337,8 @@ def main():
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="cubes per side (default: the 48^3 workload)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched leg")
     ap.add_argument("--batched-only", action="store_true", help="run only the 64-mesh batched leg")
+    ap.add_argument("--no-reacting", action="store_true", help="skip the reacting NS and learned-guess legs")
+    ap.add_argument("--reacting-only", action="store_true", help="run only the reacting NS and learned-guess legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -239,6 +363,15 @@ def main():
     if args.batched_only:
         stream = torch.cuda.Stream(device=dev)
         print(json.dumps({"batched": batched_leg(dg, wl, dev, stream, max(2, args.steps // 10))}), flush=True)
+        return
+    if args.reacting_only:
+        stream = torch.cuda.Stream(device=dev)
+        xyz, vid = wl.kuhn_box_mesh(WORKLOAD["n"], 10.0, WORKLOAD["jitter"], WORKLOAD["mesh_seed"])
+        X48 = dg.Mesh(WORKLOAD["order"], xyz, vid, 0).nodes()
+        rec = {"reacting": reacting_leg(dg, wl, dev, stream, max(2, args.steps // 5))}
+        print(json.dumps(rec), flush=True)
+        rec["learned_guess"] = learned_leg(dg, wl, dev, stream, X48)
+        print(json.dumps(rec), flush=True)
         return
     p = WORKLOAD["order"]
     xyz, vid = wl.kuhn_box_mesh(args.n, 10.0, WORKLOAD["jitter"], WORKLOAD["mesh_seed"])
@@ -306,6 +439,10 @@ def main():
         del outs
         torch.cuda.empty_cache()
         rec["batched"] = batched_leg(dg, wl, dev, stream, max(2, args.steps // 10))
+    if not args.no_reacting:
+        torch.cuda.empty_cache()
+        rec["reacting"] = reacting_leg(dg, wl, dev, stream, max(2, args.steps // 5))
+        rec["learned_guess"] = learned_leg(dg, wl, dev, stream, X)
     print(json.dumps(rec), flush=True)
 
 
