@@ -14,10 +14,19 @@ fluxes, jumps, the state and the Runge-Kutta update stay FP64.
   Op X ~ Op_hi X_hi + Op_hi X_lo + Op_lo X_hi, products accumulated in FP32.
   Each BF16 x BF16 product is exact in FP32.
 
+Delta form (both reduced modes): the volume operands are the deviations
+G_a - G_a(node 0) of each element's contravariant fluxes from their value at
+the element's first node.  The contraction is unchanged in exact arithmetic
+because every row of D_a sums to zero (D_a applied to a constant is zero),
+while the rounded operands now carry the flux variation inside the element
+instead of its level, so the error scales with that variation.
+
 Error bound used by the tests (Higham, Accuracy and Stability, Sec. 3.1,
 with the operand representation error added): for each output entry,
   |y_mode - y| <= (c_rep + K u32) * sum_k |Op_ik| |X_k|,
-u32 = 2^-24, K = number of summed terms, c_rep = 2 u32 for FP32 (both
+u32 = 2^-24, K = number of summed terms (in the delta form the |X| are
+those of the delta operands, and the FP64 reference's own rounding
+K 2^-53 sum_k |Op_ik| |X_k| on the plain operands is added), c_rep = 2 u32 for FP32 (both
 operands rounded once) and 3 * 2^-16 + 2 u32 for split BF16 (dropped lo*lo
 product, the two operands' residuals after the lo part, and their rounding to
 FP32).
@@ -70,10 +79,12 @@ def error_bound_factor(mode: str, K: int) -> float:
     return c_rep + acc
 
 
-def contraction_inputs(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: float = 1.4, elems=None):
+def contraction_inputs(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: float = 1.4, elems=None,
+                       delta: bool = False):
     """The operator [-Dr | -Ds | -Dt | LIFT] (Np x K) and the per-element,
     per-field operand X = [G_r; G_s; G_t; Delta] (shape [5, n, K]) of the
-    Euler RHS, in FP64, so that rhs = X Op^T."""
+    Euler RHS, in FP64, so that rhs = X Op^T (up to rounding).  With
+    delta=True each G_a is replaced by G_a - G_a(node 0) (delta form)."""
     from .euler import _fluxes
     E = q.shape[1]
     idx = np.arange(E) if elems is None else np.asarray(elems, dtype=np.int64)
@@ -81,6 +92,8 @@ def contraction_inputs(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: f
     (Fx, Fy, Fz), _, _ = _fluxes(qe, gamma)
     rx = geo["rst_x"][idx]
     Gs = [rx[None, :, a, 0, None] * Fx + rx[None, :, a, 1, None] * Fy + rx[None, :, a, 2, None] * Fz for a in range(3)]
+    if delta:
+        Gs = [G - G[:, :, :1] for G in Gs]
     Nfp = ops["Nfp"]
     fm = ops["Fmask"].reshape(-1)
     qM = qe[:, :, fm]
@@ -98,9 +111,16 @@ def contraction_inputs(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: f
 
 
 def rhs(ops: dict, geo: dict, conn: dict, q: np.ndarray, mode: str, gamma: float = 1.4, elems=None):
-    """Euler RHS with the contraction done in `mode`; returns (rhs, bound)
-    where bound is the per-entry error bound of that mode against FP64."""
-    Op, X = contraction_inputs(ops, geo, conn, q, gamma, elems)
+    """Euler RHS with the contraction done in `mode` (reduced modes in the
+    delta form); returns (rhs, bound) where bound is the per-entry error bound
+    of that mode against FP64."""
+    Op, X = contraction_inputs(ops, geo, conn, q, gamma, elems, delta=mode != "fp64")
     y = contract(Op, X, mode)
+    K = Op.shape[1]
     T = np.abs(X) @ np.abs(Op).T
-    return y, error_bound_factor(mode, Op.shape[1]) * T
+    bound = error_bound_factor(mode, K) * T
+    if mode != "fp64":
+        # the FP64 reference carries its own rounding, on the plain operands
+        _, Xp = contraction_inputs(ops, geo, conn, q, gamma, elems)
+        bound = bound + error_bound_factor("fp64", K) * (np.abs(Xp) @ np.abs(Op).T)
+    return y, bound

@@ -21,6 +21,12 @@
 //              computed: volume slots t = 3 s + a (node 4 s + g, direction
 //              a), then face slots t (face node 4 t + g), each padded to a
 //              multiple of 8.
+//
+// Delta form (both modes): the volume operands are G_a(node j) - G_a(node 0)
+// of the element.  Every row of D_a sums to zero, so the contraction is
+// unchanged in exact arithmetic, while the rounded operands carry the flux
+// variation inside the element instead of its level (the pressure part of
+// the momentum flux, for instance), and the rounding error shrinks with it.
 #pragma once
 #include "euler_point.hpp"
 
@@ -121,6 +127,15 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
 #pragma unroll
       for (int rb = 0; rb < C::NR; ++rb) acc[f][rb] = v4f{0.f, 0.f, 0.f, 0.f};
 
+    // fluxes of the element's node 0: the reference of the delta form
+    double G0[3][5];
+    {
+      double q0[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) q0[f] = q[f * Es + ec * C::NP];
+      contravariant_flux(q0, gm, gm1, G0);
+    }
+
     if constexpr (MODE == 1) {
       const float* op = reinterpret_cast<const float*>(s_op);
 #pragma unroll
@@ -132,6 +147,10 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
 #pragma unroll
           for (int f = 0; f < 5; ++f) qq[f] = q[f * Es + ec * C::NP + j];
           contravariant_flux(qq, gm, gm1, G);
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int f = 0; f < 5; ++f) G[r][f] -= G0[r][f];
         } else {
 #pragma unroll
           for (int r = 0; r < 3; ++r)
@@ -194,6 +213,10 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
 #pragma unroll
             for (int f = 0; f < 5; ++f) qq[f] = q[f * Es + ec * C::NP + j];
             contravariant_flux(qq, gm, gm1, G);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+              for (int f = 0; f < 5; ++f) G[a][f] -= G0[a][f];
           } else {
 #pragma unroll
             for (int a = 0; a < 3; ++a)

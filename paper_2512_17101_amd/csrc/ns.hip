@@ -200,7 +200,7 @@ struct NsRhsCfg {
 };
 
 template <int P, bool FUSED>
-__global__ __launch_bounds__(256) void ns_rhs_kernel(NsArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ns_rhs_kernel(NsArgs A) {
   using C = NsCfg<P>;
   using R = NsRhsCfg<P>;
   static_assert(kNsFields % R::H == 0, "field sets must divide the fields");
