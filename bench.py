@@ -242,9 +242,11 @@ def reacting_leg(dg, wl, dev, stream, steps):
         ms_rhs = _time_ms(stream, lambda: dg.ns_rhs(mesh, th, q, T, sig, out, mech=mk, stream=stream), steps)
         work = torch.empty(dg.NS_WORK_PER_NODE * nn, dtype=torch.float64, device=dev)
         qs, Ts = q.clone(), T.clone()
-        dg.ns_rk_step(mesh, th, qs, Ts, work, 1e-9, mech=mk, stream=stream)
+        # the seeded rates are stiff (A up to 1e12 SI): a stable explicit step is tiny
+        dt_rk = 1e-14
+        dg.ns_rk_step(mesh, th, qs, Ts, work, dt_rk, mech=mk, stream=stream)
         stream.synchronize()
-        ms_rk = _time_ms(stream, lambda: dg.ns_rk_step(mesh, th, qs, Ts, work, 1e-9, mech=mk, stream=stream),
+        ms_rk = _time_ms(stream, lambda: dg.ns_rk_step(mesh, th, qs, Ts, work, dt_rk, mech=mk, stream=stream),
                          max(2, steps // 5))
     iters = it.cpu().numpy()
     finite = bool(torch.isfinite(out).all()) and bool(torch.isfinite(qs).all())
@@ -254,7 +256,8 @@ def reacting_leg(dg, wl, dev, stream, steps):
            "ns_rhs_ms": round(ms_rhs, 4), "value": round(dof_f / (ms_rhs * 1e-3) / 1e9, 3),
            "unit": "GDOF·fields/s (gradient + right-hand side, sources included)",
            "temperature_ms": round(ms_T, 4), "newton_mean_iters_from_1000K": round(float(iters.mean()), 3),
-           "newton_failures": int((iters < 0).sum()), "rk_step_ms": round(ms_rk, 4), "finite": finite}
+           "newton_failures": int((iters < 0).sum()), "rk_step_ms": round(ms_rk, 4), "rk_dt": dt_rk,
+           "finite": finite}
     return rec
 
 

@@ -119,6 +119,11 @@ def test_ns_uniform_state_gives_zero():
 
 
 def test_ns_rk_steps_track_oracle():
+    """Three fused LSRK steps (temperature Newton, gradient and right-hand-side
+    passes per stage) track the oracle's steps.  Without sources: the seeded
+    mechanism's rates (A up to 1e12 in SI units) are far too stiff for an
+    explicit step at the acoustic limit; the sources' parity is checked on
+    the right-hand side itself."""
     dev = _dev()
     p = 2
     xyz, vid, ops, geo, conn, q0, T0 = _case(p, (3, 3, 3), state_seed=3006)
@@ -129,18 +134,17 @@ def test_ns_rk_steps_track_oracle():
     def f(qq, tt):
         T, it = ns.temperature(qq, TH)
         assert np.all(it > 0)
-        return ns.rhs(ops, geo, conn, qq, T, TH, MECH, mu=mu)
+        return ns.rhs(ops, geo, conn, qq, T, TH, None, mu=mu)
 
     qe = q0.copy()
     for s in range(3):
         qe, _ = olsrk.lsrk_step(f, qe, s * dt, dt)
     th = dg.Thermo(TH["W"], TH["a"])
-    mk = dg.Mechanism(th, MECH["A"], MECH["Ea"], MECH["nu_r"], MECH["nu_p"])
     q = torch.from_numpy(q0).to(dev)
     T = torch.full(T0.shape, 1000.0, dtype=torch.float64, device=dev)
     work = torch.empty(dg.NS_WORK_PER_NODE * mesh.E * mesh.Np, dtype=torch.float64, device=dev)
     for s in range(3):
-        dg.ns_rk_step(mesh, th, q, T, work, dt, mech=mk, mu=mu)
+        dg.ns_rk_step(mesh, th, q, T, work, dt, mech=None, mu=mu)
     torch.cuda.synchronize()
     got = q.cpu().numpy()
     n = mesh.E * mesh.Np
@@ -151,6 +155,7 @@ def test_ns_rk_steps_track_oracle():
     err = np.abs(got - qe).max(axis=(1, 2)) / scale
     change = np.abs(qe - q0).max(axis=(1, 2)) / scale
     print("3 NS steps: per-field rel diff vs oracle", err, "relative change", change)
+    assert np.all(change[1:] > 1e-9)  # the steps moved the state
     assert np.all(err <= 1e-11)
 
 
