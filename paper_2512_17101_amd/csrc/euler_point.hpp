@@ -44,12 +44,21 @@ __device__ inline void contravariant_flux(const double qq[5], const double gm[9]
 }
 
 // Face normal scaled by Fscale = sJ / J, from the metric: f0 {t=-1}: -grad t,
-// f1 {s=-1}: -grad s, f2 {r+s+t=-1}: grad r + grad s + grad t, f3 {r=-1}: -grad r.
+// f1 {s=-1}: -grad s, f2 {r+s+t=-1}: grad r + grad s + grad t, f3 {r=-1}: -grad r,
+// i.e. N = c_r grad r + c_s grad s + c_t grad t with (c_r, c_s, c_t) =
+// (0,0,-1), (0,-1,0), (1,1,1), (-1,0,0).  The coefficients are formed with
+// integer arithmetic on the face index, not a branch chain: hipcc for gfx950
+// was measured to return face 1's normal for face 3 when the chain was
+// selected by a face index that differs between lanes.  Multiplying by 0 and
+// +-1 is exact, so the result is the same vector the chain defines.
 __device__ inline void scaled_normal(int face, const double gm[9], double& Nx, double& Ny, double& Nz) {
-  if (face == 0) { Nx = -gm[6]; Ny = -gm[7]; Nz = -gm[8]; }
-  else if (face == 1) { Nx = -gm[3]; Ny = -gm[4]; Nz = -gm[5]; }
-  else if (face == 2) { Nx = gm[0] + gm[3] + gm[6]; Ny = gm[1] + gm[4] + gm[7]; Nz = gm[2] + gm[5] + gm[8]; }
-  else { Nx = -gm[0]; Ny = -gm[1]; Nz = -gm[2]; }
+  const int hi = face >> 1, lo = face & 1;
+  const double cr = static_cast<double>(hi * (1 - 2 * lo));             // 0, 0, 1, -1
+  const double cs = static_cast<double>((lo ^ hi) * (2 * hi - 1));       // 0, -1, 1, 0
+  const double ct = static_cast<double>((1 - lo) * (2 * hi - 1));        // -1, 0, 1, 0
+  Nx = cr * gm[0] + cs * gm[3] + ct * gm[6];
+  Ny = cr * gm[1] + cs * gm[4] + ct * gm[7];
+  Nz = cr * gm[2] + cs * gm[5] + ct * gm[8];
 }
 
 // Scaled local Lax-Friedrichs jump at a face node, N = Fscale n, U_n = N . u:

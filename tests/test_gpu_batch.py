@@ -38,6 +38,7 @@ def _problem(shapes=SHAPES, seed=77):
         geo = om.geometry(xyz)
         q = wl.vortex_state(om.node_coordinates(xyz, ops["rst"]), beta=rng.uniform(3, 5),
                             center=tuple(rng.uniform(3, 7, 2)))
+        q = q * (1.0 + 1e-3 * rng.standard_normal(q.shape))  # jumping face traces
         dt = oe.cfl_dt(ops, geo, q, 0.2)
         meshes.append(m)
         q0.append(q)

@@ -86,6 +86,19 @@ def test_rhs_parity_ragged_mesh(p):
     _check(c, _gpu_rhs(mesh, c["q"]), label=f"p={p} E={mesh.E}")
 
 
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_rhs_parity_discontinuous_traces(p):
+    """Per-node noise (1 %) makes every face trace jump, so the face flux, the
+    Lax-Friedrichs term and the normal of every face enter the result (a
+    smooth state sampled at nodes has no jumps and leaves the surface term
+    zero whatever the normals)."""
+    _dev()
+    c = _case(p, (3, 4, 5), pert_seed=7)
+    c["q"] = np.ascontiguousarray(c["q"] * (1.0 + 0.01 * np.random.default_rng(p).standard_normal(c["q"].shape)))
+    mesh = dg.Mesh(p, c["xyz"], c["vid"])
+    _check(c, _gpu_rhs(mesh, c["q"]), label=f"p={p} E={mesh.E} noisy")
+
+
 def test_rhs_parity_vortex_p2_4cubed():
     """384 tets, p = 2, +-5 % jitter, isentropic vortex (the small workload)."""
     _dev()

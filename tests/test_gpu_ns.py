@@ -26,7 +26,7 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def _case(p, dims, seed=1003, state_seed=3005, jitter=0.03):
+def _case(p, dims, seed=1003, state_seed=3005, jitter=0.03, noise=1e-3):
     xyz, vid = wl.kuhn_mesh(dims, (L * dims[0] / max(dims), L * dims[1] / max(dims), L * dims[2] / max(dims)),
                             jitter, seed)
     ops = ore.operators(p)
@@ -34,6 +34,8 @@ def _case(p, dims, seed=1003, state_seed=3005, jitter=0.03):
     conn = om.connectivity(vid, p)
     X = om.node_coordinates(xyz, ops["rst"])
     q = wl.reacting_state(X.reshape(-1, 3), seed=state_seed, L=L, n_cells=max(dims)).reshape((12,) + X.shape[:2])
+    # per-node noise: every face trace of q (and so of T and the gradients) jumps
+    q = q * (1.0 + noise * np.random.default_rng(state_seed).standard_normal(q.shape))
     T, it = ns.temperature(q, TH)
     assert np.all(it > 0)
     return xyz, vid, ops, geo, conn, np.ascontiguousarray(q), T

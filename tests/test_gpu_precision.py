@@ -50,6 +50,20 @@ def test_reduced_precision_rhs_within_bound(p, mode):
     assert np.all(err <= bound)
 
 
+@pytest.mark.parametrize("mode", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_reduced_precision_rhs_within_bound_discontinuous(p, mode):
+    """Same bound with 1 % per-node noise, so every face jump is nonzero."""
+    xyz, vid, ops, geo, conn, q = _case(p, (3, 4, 5))
+    q = np.ascontiguousarray(q * (1.0 + 0.01 * np.random.default_rng(10 + p).standard_normal(q.shape)))
+    mesh = dg.Mesh(p, xyz, vid)
+    got = _gpu(mesh, q, mode)
+    r64 = oe.rhs(ops, geo, conn, q)
+    _, bound = opr.rhs(ops, geo, conn, q, mode)
+    print(f"p={p} {mode} noisy: max err/bound {np.max(np.abs(got - r64) / bound):.3f}")
+    assert np.all(np.abs(got - r64) <= bound)
+
+
 def test_split_bf16_far_better_than_its_bf16_part():
     """The lo terms are really used: the split result is >30x closer to FP64
     than BF16-only operands would be (emulated on the same inputs)."""
