@@ -100,20 +100,44 @@ __device__ inline void split_mma(const v8bf* __restrict__ op, int k, int lane, f
 
 // One 16-element tile of one mesh: the whole right-hand side (or fused
 // Runge-Kutta stage) of elements 16 tile .. 16 tile + 15.  `op` is the
-// operator table in the mode's layout, nb / fm the face tables.
-template <int P, int MODE, bool FUSED>
+// operator table in the mode's layout, nb / fm the face tables.  With
+// STAGED, `sq` is this wave's LDS buffer of 5 x 16 Np doubles: the tile's
+// state is first copied there with coalesced loads, and own traces and
+// neighbour traces inside the tile are read from it.
+template <int P, int MODE, bool FUSED, bool STAGED = false>
 __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ s_op, const uint8_t* __restrict__ s_nb,
-                                 const int* __restrict__ s_fm, int64_t tile) {
+                                 const int* __restrict__ s_fm, int64_t tile, double* __restrict__ sq = nullptr) {
   using C = LCfg<P>;
+  constexpr int TQ = 16 * C::NP;
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const int64_t Es = A.E * C::NP;
   const double* __restrict__ q = A.q;
   const double gm1 = A.gamma - 1.0;
+  const int64_t e0 = tile * 16;
+  if constexpr (STAGED) {
+    const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const double* src = q + f * Es + e0 * C::NP;
+#pragma unroll
+      for (int k = 0; k < (TQ + 63) / 64; ++k) {
+        const int i = 64 * k + lane;
+        if (i < nval) sq[f * TQ + i] = src[i];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
   {
-    const int64_t e = tile * 16 + n;
+    const int64_t e = e0 + n;
     const bool valid = e < A.E;
     const int64_t ec = valid ? e : A.E - 1;
+    const int nl = static_cast<int>(ec - e0);  // element row in the tile
+    // own-element node value of field f (staged tile or memory)
+    auto own_q = [&](int f, int j) -> double {
+      if constexpr (STAGED) return sq[f * TQ + nl * C::NP + j];
+      else return q[f * Es + ec * C::NP + j];
+    };
     double gm[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) gm[c] = A.geo[c * A.Epad + ec];
@@ -132,7 +156,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
     {
       double q0[5];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) q0[f] = q[f * Es + ec * C::NP];
+      for (int f = 0; f < 5; ++f) q0[f] = own_q(f, 0);
       contravariant_flux(q0, gm, gm1, G0);
     }
 
@@ -145,7 +169,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
         if (j < C::NP) {
           double qq[5];
 #pragma unroll
-          for (int f = 0; f < 5; ++f) qq[f] = q[f * Es + ec * C::NP + j];
+          for (int f = 0; f < 5; ++f) qq[f] = own_q(f, j);
           contravariant_flux(qq, gm, gm1, G);
 #pragma unroll
           for (int r = 0; r < 3; ++r)
@@ -176,10 +200,16 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
         const int own = s_fm[fm];
         const int jp = s_nb[(face * 24 + c.y) * C::NFP + mm];
         double qm[5], qp[5], D[5];
+        const int64_t nloc = static_cast<int64_t>(c.x) - e0;
+        const bool in_tile = STAGED && nloc >= 0 && nloc < 16;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-          qm[f] = q[f * Es + ec * C::NP + own];
-          qp[f] = q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
+          qm[f] = own_q(f, own);
+          if constexpr (STAGED)
+            qp[f] = in_tile ? sq[f * TQ + static_cast<int>(nloc) * C::NP + jp]
+                            : q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
+          else
+            qp[f] = q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
         }
         double Nx, Ny, Nz;
         scaled_normal(face, gm, Nx, Ny, Nz);
@@ -211,7 +241,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
           if (j < C::NP) {
             double qq[5];
 #pragma unroll
-            for (int f = 0; f < 5; ++f) qq[f] = q[f * Es + ec * C::NP + j];
+            for (int f = 0; f < 5; ++f) qq[f] = own_q(f, j);
             contravariant_flux(qq, gm, gm1, G);
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -237,10 +267,16 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
         const int own = s_fm[fm];
         const int jp = s_nb[(face * 24 + c.y) * C::NFP + mm];
         double qm[5], qp[5], D[5];
+        const int64_t nloc = static_cast<int64_t>(c.x) - e0;
+        const bool in_tile = STAGED && nloc >= 0 && nloc < 16;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-          qm[f] = q[f * Es + ec * C::NP + own];
-          qp[f] = q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
+          qm[f] = own_q(f, own);
+          if constexpr (STAGED)
+            qp[f] = in_tile ? sq[f * TQ + static_cast<int>(nloc) * C::NP + jp]
+                            : q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
+          else
+            qp[f] = q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
         }
         double Nx, Ny, Nz;
         scaled_normal(face, gm, Nx, Ny, Nz);

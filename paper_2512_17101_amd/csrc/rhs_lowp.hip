@@ -1,5 +1,6 @@
 // Euler right-hand side with reduced-precision element contractions, gfx950:
-// the single-mesh persistent kernel over the tile routine of lowp_tile.hpp.
+// the single-mesh kernel over the tile routine of lowp_tile.hpp, one wave per
+// 16-element tile with the tile's state staged in LDS.
 #include "internal.hpp"
 #include "lowp_tile.hpp"
 
@@ -9,59 +10,47 @@ namespace {
 using namespace lowp;
 
 constexpr int kWaves = 4;
-constexpr int kXcds = 8;
+
+// Waves per block (one 16-element tile each; the tile's state is staged in
+// LDS, 5 x 16 Np doubles per wave) and the register target: three waves per
+// SIMD up to p = 3, two at p = 4.
+template <int P>
+constexpr int lowp_waves() { return P >= 4 ? 2 : kWaves; }
+template <int P, int MODE>
+constexpr int lowp_wpe() { return P < 4 ? 3 : 2; }
 
 template <int P, int MODE, bool FUSED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void rhs_euler_lowp_kernel(LowArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(lowp_wpe<P, MODE>()))) void rhs_euler_lowp_kernel(
+    LowArgs A) {
   using C = LCfg<P>;
-  constexpr int OPN = MODE == 1 ? C::OP32 : C::OPBF / 2;  // 32-bit words
-  __shared__ uint32_t s_op[OPN];
+  constexpr int W = lowp_waves<P>();
+  __shared__ double s_q[W][5 * 16 * C::NP];
   __shared__ uint8_t s_nb[4 * 24 * C::NFP];
   __shared__ int s_fm[4 * C::NFP];
-  {
-    const uint32_t* src = MODE == 1 ? reinterpret_cast<const uint32_t*>(A.op32)
-                                    : reinterpret_cast<const uint32_t*>(A.opbf);
-    for (int i = threadIdx.x; i < OPN; i += blockDim.x) s_op[i] = src[i];
-    for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nb[i] = A.nbtab[i];
-    for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fm[i] = A.fmask[i];
-  }
+  for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nb[i] = A.nbtab[i];
+  for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fm[i] = A.fmask[i];
   __syncthreads();
+  // the operator table is read from memory (cache-resident): LDS holds the states
+  const uint32_t* op = MODE == 1 ? reinterpret_cast<const uint32_t*>(A.op32) : reinterpret_cast<const uint32_t*>(A.opbf);
   const int wave = threadIdx.x >> 6;
-  const int xcd = blockIdx.x % kXcds;
-  const int slot = blockIdx.x / kXcds;
-  const int nslots = (static_cast<int>(gridDim.x) - xcd + kXcds - 1) / kXcds;
-  const int64_t T = A.ntiles;
-  const int64_t t_begin = T * xcd / kXcds, t_end = T * (xcd + 1) / kXcds;
-  for (int64_t tile = t_begin + slot * kWaves + wave; tile < t_end; tile += static_cast<int64_t>(nslots) * kWaves)
-    lowp_tile<P, MODE, FUSED>(A, s_op, s_nb, s_fm, tile);
+  const int64_t tile = static_cast<int64_t>(blockIdx.x) * W + wave;
+  if (tile < A.ntiles) lowp_tile<P, MODE, FUSED, true>(A, op, s_nb, s_fm, tile, s_q[wave]);
 }
 
 template <int P, int MODE, bool FUSED>
 int lowp_grid(const Mesh& m) {
-  static int blocks_per_cu = -1;
-  static int cus = 0;
-  if (blocks_per_cu < 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rhs_euler_lowp_kernel<P, MODE, FUSED>, 64 * kWaves, 0) !=
-            hipSuccess || nb < 1)
-      nb = 1;
-    hipDeviceProp_t prop;
-    cus = hipGetDeviceProperties(&prop, m.device) == hipSuccess ? prop.multiProcessorCount : 256;
-    blocks_per_cu = nb;
-  }
   const int64_t tiles = m.Epad / 16;
-  const int64_t needed = (tiles + kWaves - 1) / kWaves;
-  int64_t grid = static_cast<int64_t>(blocks_per_cu) * cus;
-  if (grid > needed) grid = (needed + kXcds - 1) / kXcds * kXcds;
-  return static_cast<int>(grid < 1 ? 1 : grid);
+  constexpr int W = lowp_waves<P>();
+  return static_cast<int>((tiles + W - 1) / W);
 }
 
 template <int P, int MODE>
 dg_status launch_lowp_p(const Mesh& m, const LowArgs& args, bool fused, hipStream_t s) {
+  constexpr int W = lowp_waves<P>();
   if (fused)
-    rhs_euler_lowp_kernel<P, MODE, true><<<lowp_grid<P, MODE, true>(m), 64 * kWaves, 0, s>>>(args);
+    rhs_euler_lowp_kernel<P, MODE, true><<<lowp_grid<P, MODE, true>(m), 64 * W, 0, s>>>(args);
   else
-    rhs_euler_lowp_kernel<P, MODE, false><<<lowp_grid<P, MODE, false>(m), 64 * kWaves, 0, s>>>(args);
+    rhs_euler_lowp_kernel<P, MODE, false><<<lowp_grid<P, MODE, false>(m), 64 * W, 0, s>>>(args);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
