@@ -254,33 +254,39 @@ dg_status dg_ns_rk_step(dg_mesh m, const dg_params* prm, double* q, double* T, d
 
 /* ---- batched stepping of many meshes ------------------------------------ */
 /* A batch advances many independent meshes of mixed order (p = 1..4) and
- * size with one kernel launch per Runge-Kutta stage: a work list holds one
- * item per (mesh, 16-element tile) of every mesh, and a persistent kernel
- * walks it, running each item with that mesh's order.  This is the launch
- * counterpart of concatenating independent calls into one larger call
- * (Sec. 4.2, "Concatenation of Function Calls"), aimed at the per-launch floor
- * that small meshes hit (Sec. 5.2, MIRGE-Com vs. MFEM).  Each mesh's result is
+ * size with a few kernel launches per Runge-Kutta stage: a work list holds
+ * one item per (mesh, 16-element tile) of every mesh.  In the mixed mode one
+ * persistent kernel per stage walks the whole list, running each item with
+ * its mesh's order; in the per-order mode one kernel per order present and
+ * stage walks that order's items, the chains of different orders running
+ * concurrently on forked streams.  This is the launch counterpart of
+ * concatenating independent calls into one larger call (Sec. 4.2,
+ * "Concatenation of Function Calls"), aimed at the per-launch floor that
+ * small meshes hit (Sec. 5.2, MIRGE-Com vs. MFEM).  Each mesh's result is
  * bitwise the one dg_rk_step gives it alone at the same precision, because
- * both run the same tile routine.  Contractions are DG_FP32 or DG_SPLIT_BF16
- * (DG_FP64 returns DG_ERR_UNSUPPORTED); the state and stage update are FP64.
- * A batch keeps pointers to the bound caller buffers (and, once a step was
- * run with use_graph, a captured graph that holds them): they must stay
- * valid until the next bind or destroy.  Calls on one batch must not
- * overlap. */
+ * both modes run the same tile routine.  Contractions are DG_FP32 or
+ * DG_SPLIT_BF16 (DG_FP64 returns DG_ERR_UNSUPPORTED); the state and stage
+ * update are FP64.  A batch keeps pointers to the bound caller buffers (and,
+ * once a step was run with use_graph, a captured graph that holds them): they
+ * must stay valid until the next bind or destroy.  Calls on one batch must
+ * not overlap. */
 typedef struct dg_batch_s* dg_batch;
 
-/* Launch shape of the batched stage kernel. */
+/* Launch shape of the batched stage kernels. */
 typedef struct {
   int waves_per_block; /* 2, 4 or 8 (64 lanes each) */
   int blocks_per_cu;   /* 1..4, capped by the kernel's occupancy */
   int order;           /* work-list order: 0 = highest order first, 1 = mesh order */
   int xcd_chunks;      /* 1 = each of the 8 XCDs walks a contiguous eighth of the
                           list, 0 = the whole grid strides over the list */
+  int per_order;       /* 1 = per-order launches (the four fields above are
+                          then unused: each order's kernel has its own fixed
+                          shape), 0 = one mixed-order launch per stage */
 } dg_batch_config;
 
 /* Meshes (n >= 1, all on the same device, not freed while the batch lives)
  * and the contraction precision.  Builds and uploads the work lists; the
- * initial launch shape is {4, 2, 0, 0}. */
+ * initial launch shape is {4, 2, 0, 0, 1}. */
 dg_status dg_batch_create(const dg_mesh* meshes, int n, dg_precision prec, dg_batch* out);
 dg_status dg_batch_destroy(dg_batch b);
 /* Bind the state of every mesh: q[i] device [5][E_i][Np_i] (updated in
@@ -292,15 +298,18 @@ dg_status dg_batch_bind(dg_batch b, double* const* q, double* const* work, const
 dg_status dg_batch_set_config(dg_batch b, const dg_batch_config* cfg);
 dg_status dg_batch_get_config(dg_batch b, dg_batch_config* cfg);
 /* One LSRK(5,4) step of every bound mesh: five stage launches and one copy
- * launch.  use_graph != 0 replays a graph of those six launches on `stream`,
- * capturing it first when none matches the current binding, configuration
- * and gamma; use_graph == 0 launches them directly. */
+ * launch (per order present in the per-order mode).  use_graph != 0 replays
+ * a graph of those launches on `stream`, capturing it first when none
+ * matches the current binding, configuration and gamma; use_graph == 0
+ * launches them directly (forking to the batch's own streams and joining
+ * back into `stream` in the per-order mode). */
 dg_status dg_batch_rk_step(dg_batch b, const dg_params* prm, int use_graph, hipStream_t stream);
 /* Work items, total elements, and kernel nodes of the captured graph (0 when
  * none is held).  Any pointer may be NULL. */
 dg_status dg_batch_info(dg_batch b, int64_t* n_items, int64_t* n_elem, int* graph_kernel_nodes);
-/* Time every candidate launch shape (waves_per_block x blocks_per_cu x order
- * x xcd_chunks) with `trials` steps each after one warm-up step on the bound
+/* Time every candidate launch shape (the per-order mode, and the mixed mode
+ * at waves_per_block x blocks_per_cu x order x xcd_chunks) with `trials`
+ * steps each after one warm-up step on the bound
  * buffers, keep the fastest and set it.  The bound q are saved before and
  * restored after (a temporary device copy), so tuning leaves the state as it
  * was; work is overwritten.  With cache_path != NULL the choice is looked up

@@ -26,15 +26,17 @@ struct BatchItem {
   int tile;
 };
 
-// Reference-element tables of every order present in the batch, staged in
-// LDS by each block: words[p] 32-bit words of operator table at op[p] go to
-// LDS word op_off[p]; the face tables follow (nb bytes, fm ints).
+// Face tables of every order present in the batch, staged in LDS by each
+// block of the mixed-order kernel (nb bytes at nb_off[p], fm ints at
+// fm_off[p]); the operator tables op[p] are read from memory.  The
+// per-order kernels stage their own order's tables and one state tile per
+// wave in static LDS.
 struct BatchTables {
   const uint32_t* op[5];
   const uint8_t* nb[5];
   const int* fm[5];
-  int op_words[5], nb_bytes[5], fm_n[5];
-  int op_off[5], nb_off[5], fm_off[5];  // byte offsets into LDS
+  int nb_bytes[5], fm_n[5];
+  int nb_off[5], fm_off[5];  // byte offsets into LDS
   int lds_bytes;
 };
 
@@ -42,17 +44,25 @@ struct BatchLaunch {
   const BatchMesh* meshes;
   const BatchItem* items;
   int64_t n_items;
+  // items [p_begin[p], p_end[p]) of the list have order p (the list of the
+  // per-order launches is grouped by order)
+  int64_t p_begin[5], p_end[5];
   const double* dt;  // [n meshes]
   double gamma;
   BatchTables tabs;
   int waves_per_block, blocks, xcd_chunks;
 };
 
-// Stage s of the LSRK scheme over every item: reads q (odd == 0) or tmp
-// (odd == 1), writes the other, res <- a res + dt rhs.
+// Stage s of the LSRK scheme over every item (one persistent launch of the
+// mixed-order kernel): reads q (odd == 0) or tmp (odd == 1), writes the
+// other, res <- a res + dt rhs.
 dg_status launch_batch_stage(dg_precision prec, const BatchLaunch& L, double a, double b, int odd, hipStream_t s);
-// q <- tmp for every item's elements.
-dg_status launch_batch_copy(const BatchLaunch& L, hipStream_t s);
+// The same stage over the items of order p only, with the kernel specialised
+// for that order (one wave per item).
+dg_status launch_batch_order_stage(dg_precision prec, const BatchLaunch& L, int p, double a, double b, int odd,
+                                   hipStream_t s);
+// q <- tmp for the elements of items [begin, end).
+dg_status launch_batch_copy(const BatchLaunch& L, int64_t begin, int64_t end, hipStream_t s);
 // Largest resident blocks per CU of the stage kernel for a launch shape.
 int batch_stage_occupancy(dg_precision prec, int waves_per_block, int lds_bytes);
 // Allows the stage kernels their dynamic LDS size (once per device and size).

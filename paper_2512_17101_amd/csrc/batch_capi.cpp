@@ -34,10 +34,13 @@ struct dg_batch_s {
   BatchMesh* d_meshes = nullptr;
   BatchItem* d_items[2] = {nullptr, nullptr};  // by dg_batch_config::order
   std::vector<BatchMesh> host_meshes;
+  int64_t p_begin[5] = {0, 0, 0, 0, 0}, p_end[5] = {0, 0, 0, 0, 0};  // in list 0 (grouped by order)
   const double* dt = nullptr;
   bool bound = false;
-  dg_batch_config cfg{4, 2, 0, 0};
+  dg_batch_config cfg{4, 2, 0, 0, 1};
   hipStream_t cap_stream = nullptr;
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};  // per-order chains after the first
+  hipEvent_t fork_ev = nullptr, join_ev[3] = {nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   double graph_gamma = 0.0;
@@ -52,6 +55,11 @@ struct dg_batch_s {
   ~dg_batch_s() {
     drop_graph();
     if (cap_stream) hipStreamDestroy(cap_stream);
+    for (hipStream_t x : side)
+      if (x) hipStreamDestroy(x);
+    if (fork_ev) hipEventDestroy(fork_ev);
+    for (hipEvent_t e : join_ev)
+      if (e) hipEventDestroy(e);
     hipFree(d_meshes);
     hipFree(d_items[0]);
     hipFree(d_items[1]);
@@ -64,7 +72,8 @@ bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0
 
 bool valid_config(const dg_batch_config& c) {
   return (c.waves_per_block == 2 || c.waves_per_block == 4 || c.waves_per_block == 8) && c.blocks_per_cu >= 1 &&
-         c.blocks_per_cu <= kMaxBlocksPerCu && (c.order == 0 || c.order == 1) && (c.xcd_chunks == 0 || c.xcd_chunks == 1);
+         c.blocks_per_cu <= kMaxBlocksPerCu && (c.order == 0 || c.order == 1) &&
+         (c.xcd_chunks == 0 || c.xcd_chunks == 1) && (c.per_order == 0 || c.per_order == 1);
 }
 
 // Resolves a configuration into a launch: grid size from the CU count, the
@@ -79,8 +88,12 @@ dg_status make_launch(const dg_batch_s& b, const dg_batch_config& c, double gamm
   if (c.xcd_chunks) blocks = std::max<int64_t>(kXcds, (blocks + kXcds - 1) / kXcds * kXcds);
   if (blocks < 1) blocks = 1;
   L.meshes = b.d_meshes;
-  L.items = b.d_items[c.order];
+  L.items = b.d_items[c.per_order ? 0 : c.order];
   L.n_items = b.n_items;
+  for (int p = 0; p < 5; ++p) {
+    L.p_begin[p] = b.p_begin[p];
+    L.p_end[p] = b.p_end[p];
+  }
   L.dt = b.dt;
   L.gamma = gamma;
   L.tabs = b.tabs;
@@ -90,17 +103,41 @@ dg_status make_launch(const dg_batch_s& b, const dg_batch_config& c, double gamm
   return DG_OK;
 }
 
-// The six launches of one step: five fused stages (q -> tmp -> q ... ending in
-// tmp) and the copy back to q.
+// The launches of one step: five fused stages (q -> tmp -> q ... ending in
+// tmp) and the copy back to q.  In the per-order mode each order present has
+// its own chain of six launches; the first runs on s, the others on the
+// batch's side streams, forked from s and joined back into it.
 dg_status enqueue_step(const dg_batch_s& b, const dg_batch_config& c, double gamma, hipStream_t s) {
   BatchLaunch L;
   dg_status st = make_launch(b, c, gamma, L);
   if (st != DG_OK) return st;
-  for (int k = 0; k < 5; ++k) {
-    st = launch_batch_stage(b.prec, L, kLsrkA[k], kLsrkB[k], k & 1, s);
-    if (st != DG_OK) return st;
+  if (!c.per_order) {
+    for (int k = 0; k < 5; ++k) {
+      st = launch_batch_stage(b.prec, L, kLsrkA[k], kLsrkB[k], k & 1, s);
+      if (st != DG_OK) return st;
+    }
+    return launch_batch_copy(L, 0, L.n_items, s);
   }
-  return launch_batch_copy(L, s);
+  std::vector<int> orders;
+  for (int p = 4; p >= 1; --p)
+    if (b.p_end[p] > b.p_begin[p]) orders.push_back(p);
+  if (orders.size() > 1) {
+    DG_HIP(hipEventRecord(b.fork_ev, s));
+    for (size_t j = 1; j < orders.size(); ++j) DG_HIP(hipStreamWaitEvent(b.side[j - 1], b.fork_ev, 0));
+  }
+  for (size_t j = 0; j < orders.size(); ++j) {
+    const int p = orders[j];
+    hipStream_t sj = j == 0 ? s : b.side[j - 1];
+    for (int k = 0; k < 5 && st == DG_OK; ++k) st = launch_batch_order_stage(b.prec, L, p, kLsrkA[k], kLsrkB[k], k & 1, sj);
+    if (st == DG_OK) st = launch_batch_copy(L, b.p_begin[p], b.p_end[p], sj);
+    if (j > 0) {
+      // join even after a failed launch, so a capture in progress stays well formed
+      const hipError_t e1 = hipEventRecord(b.join_ev[j - 1], sj);
+      const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, b.join_ev[j - 1], 0) : e1;
+      if (st == DG_OK && e2 != hipSuccess) st = hip_fail(e2, "dg_batch: stream join");
+    }
+  }
+  return st;
 }
 
 dg_status capture(dg_batch_s& b, double gamma) {
@@ -127,12 +164,13 @@ dg_status capture(dg_batch_s& b, double gamma) {
 
 bool same_cfg(const dg_batch_config& a, const dg_batch_config& c) {
   return a.waves_per_block == c.waves_per_block && a.blocks_per_cu == c.blocks_per_cu && a.order == c.order &&
-         a.xcd_chunks == c.xcd_chunks;
+         a.xcd_chunks == c.xcd_chunks && a.per_order == c.per_order;
 }
 
 dg_status set_config(dg_batch_s& b, const dg_batch_config& c) {
   if (!valid_config(c))
-    return fail(DG_ERR_ARG, "dg_batch: waves_per_block in {2,4,8}, blocks_per_cu in 1..4, order and xcd_chunks in {0,1}");
+    return fail(DG_ERR_ARG,
+                "dg_batch: waves_per_block in {2,4,8}, blocks_per_cu in 1..4, order, xcd_chunks and per_order in {0,1}");
   const dg_status st = batch_prepare(b.prec, c.waves_per_block, b.tabs.lds_bytes);
   if (st != DG_OK) return st;
   b.cfg = c;
@@ -202,11 +240,12 @@ bool field(const std::string& obj, const char* name, double& v) {
 }
 
 bool parse_entry(const std::string& obj, dg_batch_config& c) {
-  double w, bp, o, x;
+  double w, bp, o, x, po;
   if (!field(obj, "waves_per_block", w) || !field(obj, "blocks_per_cu", bp) || !field(obj, "order", o) ||
-      !field(obj, "xcd_chunks", x))
+      !field(obj, "xcd_chunks", x) || !field(obj, "per_order", po))
     return false;
-  c = dg_batch_config{static_cast<int>(w), static_cast<int>(bp), static_cast<int>(o), static_cast<int>(x)};
+  c = dg_batch_config{static_cast<int>(w), static_cast<int>(bp), static_cast<int>(o), static_cast<int>(x),
+                      static_cast<int>(po)};
   return valid_config(c);
 }
 
@@ -260,29 +299,22 @@ extern "C" dg_status dg_batch_create(const dg_mesh* meshes, int n, dg_precision 
   int off = 0;
   for (const Mesh* m : b->meshes) {
     const int p = m->p;
-    if (b->tabs.op_words[p]) continue;
+    if (b->tabs.op[p]) continue;
     const LowpLayout L = lowp_layout(p);
-    const int words = prec == DG_FP32 ? L.KS32 * L.NR * 64 : (L.VKS + L.FKS) * L.NR * 2 * 64 * 8 / 2;
     b->tabs.op[p] = prec == DG_FP32 ? reinterpret_cast<const uint32_t*>(m->d_op32)
                                     : reinterpret_cast<const uint32_t*>(m->d_opbf);
     b->tabs.nb[p] = m->d_nbtab;
     b->tabs.fm[p] = m->d_fmask;
-    b->tabs.op_words[p] = words;
     b->tabs.nb_bytes[p] = 4 * 24 * L.Nfp;
     b->tabs.fm_n[p] = 4 * L.Nfp;
   }
   for (int p = 1; p <= 4; ++p) {
-    if (!b->tabs.op_words[p]) continue;
-    b->tabs.op_off[p] = off;
-    off += (b->tabs.op_words[p] * 4 + 15) / 16 * 16;
-  }
-  for (int p = 1; p <= 4; ++p) {
-    if (!b->tabs.op_words[p]) continue;
+    if (!b->tabs.op[p]) continue;
     b->tabs.fm_off[p] = off;
     off += (b->tabs.fm_n[p] * 4 + 15) / 16 * 16;
   }
   for (int p = 1; p <= 4; ++p) {
-    if (!b->tabs.op_words[p]) continue;
+    if (!b->tabs.op[p]) continue;
     b->tabs.nb_off[p] = off;
     off += (b->tabs.nb_bytes[p] + 15) / 16 * 16;
   }
@@ -303,6 +335,11 @@ extern "C" dg_status dg_batch_create(const dg_mesh* meshes, int n, dg_precision 
     }
   }
   b->n_items = static_cast<int64_t>(items[0].size());
+  for (int64_t k = 0; k < b->n_items; ++k) {  // list 0 is grouped by order
+    const int p = b->meshes[items[0][k].mesh]->p;
+    if (b->p_end[p] == 0) b->p_begin[p] = k;
+    b->p_end[p] = k + 1;
+  }
   for (const Mesh* m : b->meshes) b->n_elem += m->E;
   for (int o = 0; o < 2; ++o) {
     if (hipMalloc(&b->d_items[o], std::max<size_t>(1, items[o].size()) * sizeof(BatchItem)) != hipSuccess)
@@ -313,6 +350,9 @@ extern "C" dg_status dg_batch_create(const dg_mesh* meshes, int n, dg_precision 
     return fail(DG_ERR_ALLOC, "dg_batch_create: descriptor allocation failed");
   b->host_meshes.resize(n);
   DG_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  for (hipStream_t& x : b->side) DG_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+  DG_HIP(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  for (hipEvent_t& e : b->join_ev) DG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   const dg_status st = set_config(*b, b->cfg);
   if (st != DG_OK) return st;
   *out = b.release();
@@ -466,38 +506,39 @@ extern "C" dg_status dg_batch_autotune(dg_batch b, const dg_params* prm, const c
   dg_batch_config best = prev;
   double best_t = -1.0;
   dg_status st = DG_OK;
-  for (int w : {2, 4, 8})
-    for (int bp = 1; bp <= kMaxBlocksPerCu && st == DG_OK; ++bp) {
-      if (bp > 1 && bp > batch_stage_occupancy(b->prec, w, b->tabs.lds_bytes)) break;  // same grid as the cap
-      for (int o = 0; o < 2 && st == DG_OK; ++o)
-        for (int x = 0; x < 2 && st == DG_OK; ++x) {
-          const dg_batch_config c{w, bp, o, x};
-          st = set_config(*b, c);
-          if (st != DG_OK) break;
-          st = enqueue_step(*b, c, prm->gamma, stream);  // warm-up
-          if (st != DG_OK) break;
-          if (hipEventRecord(e0, stream) != hipSuccess) {
-            st = fail(DG_ERR_HIP, "dg_batch_autotune: hipEventRecord failed");
-            break;
-          }
-          for (int t = 0; t < trials && st == DG_OK; ++t) st = enqueue_step(*b, c, prm->gamma, stream);
-          if (st != DG_OK) break;
-          if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            st = fail(DG_ERR_HIP, "dg_batch_autotune: event timing failed");
-            break;
-          }
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            st = fail(DG_ERR_HIP, "dg_batch_autotune: hipEventElapsedTime failed");
-            break;
-          }
-          const double per = static_cast<double>(ms) / trials;
-          if (best_t < 0.0 || per < best_t) {
-            best_t = per;
-            best = c;
-          }
-        }
+  std::vector<dg_batch_config> cands{dg_batch_config{4, 2, 0, 0, 1}};
+  for (int w : {2, 4, 8}) {
+    const int occ = batch_stage_occupancy(b->prec, w, b->tabs.lds_bytes);
+    for (int bp = 1; bp <= std::min(occ, kMaxBlocksPerCu); ++bp)  // more than occ: the same grid as the cap
+      for (int o = 0; o < 2; ++o)
+        for (int x = 0; x < 2; ++x) cands.push_back(dg_batch_config{w, bp, o, x, 0});
+  }
+  for (const dg_batch_config& c : cands) {
+    st = set_config(*b, c);
+    if (st != DG_OK) break;
+    st = enqueue_step(*b, c, prm->gamma, stream);  // warm-up
+    if (st != DG_OK) break;
+    if (hipEventRecord(e0, stream) != hipSuccess) {
+      st = fail(DG_ERR_HIP, "dg_batch_autotune: hipEventRecord failed");
+      break;
     }
+    for (int t = 0; t < trials && st == DG_OK; ++t) st = enqueue_step(*b, c, prm->gamma, stream);
+    if (st != DG_OK) break;
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = fail(DG_ERR_HIP, "dg_batch_autotune: event timing failed");
+      break;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(DG_ERR_HIP, "dg_batch_autotune: hipEventElapsedTime failed");
+      break;
+    }
+    const double per = static_cast<double>(ms) / trials;
+    if (best_t < 0.0 || per < best_t) {
+      best_t = per;
+      best = c;
+    }
+  }
   // restore the bound states whatever happened
   {
     size_t o = 0;
@@ -518,8 +559,10 @@ extern "C" dg_status dg_batch_autotune(dg_batch b, const dg_params* prm, const c
   if (best_ms) *best_ms = best_t;
   if (cache_path) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "{\"waves_per_block\": %d, \"blocks_per_cu\": %d, \"order\": %d, \"xcd_chunks\": %d, \"ms\": %.6g}",
-                  best.waves_per_block, best.blocks_per_cu, best.order, best.xcd_chunks, best_t);
+    std::snprintf(buf, sizeof buf,
+                  "{\"waves_per_block\": %d, \"blocks_per_cu\": %d, \"order\": %d, \"xcd_chunks\": %d, "
+                  "\"per_order\": %d, \"ms\": %.6g}",
+                  best.waves_per_block, best.blocks_per_cu, best.order, best.xcd_chunks, best.per_order, best_t);
     cache[key] = buf;
     if (!write_cache(cache_path, cache))
       return fail(DG_ERR_ARG, std::string("dg_batch_autotune: cannot write cache file ") + cache_path);

@@ -202,21 +202,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 4 ? 2 
     }
   }
 
-  // ---- store: lane (n, g) holds rows 16 rb + 4 v + g and 16 NB16 + 4 rb4 + g
-  if (!valid) return;
+  // ---- store through this wave's LDS tile buffer (the state is no longer
+  // needed there): lane (n, g) holds rows 16 rb + 4 v + g and 16 NB16 + 4 rb4 + g
+  // of element n; the tile's outputs of one field are contiguous in memory,
+  // so they leave with coalesced stores.
+  __builtin_amdgcn_wave_barrier();
+  if (valid) {
 #pragma unroll
-  for (int f = 0; f < 5; ++f) {
+    for (int f = 0; f < 5; ++f) {
 #pragma unroll
-    for (int rb = 0; rb < C::NB16; ++rb)
+      for (int rb = 0; rb < C::NB16; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        emit<FUSED>(f * Es + e * C::NP + 16 * rb + 4 * v + g, acc16[f][rb][v], A.rhs, A.res, A.qout, q, A.a, A.b,
-                    A.dt);
+        for (int v = 0; v < 4; ++v) sq[f * TL::TQ + n * C::NP + 16 * rb + 4 * v + g] = acc16[f][rb][v];
 #pragma unroll
-    for (int rb = 0; rb < C::NB4; ++rb) {
-      const int row = 16 * C::NB16 + 4 * rb + g;
-      if (row < C::NP) emit<FUSED>(f * Es + e * C::NP + row, acc4[f][rb], A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
+      for (int rb = 0; rb < C::NB4; ++rb) {
+        const int row = 16 * C::NB16 + 4 * rb + g;
+        if (row < C::NP) sq[f * TL::TQ + n * C::NP + row] = acc4[f][rb];
+      }
     }
+  }
+  __builtin_amdgcn_wave_barrier();
+  {
+    const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+      for (int k = 0; k < (TL::TQ + 63) / 64; ++k) {
+        const int i = 64 * k + lane;
+        if (i < nval) emit<FUSED>(f * Es + e0 * C::NP + i, sq[f * TL::TQ + i], A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
+      }
   }
 }
 

@@ -44,9 +44,9 @@ class _Params(ctypes.Structure):
 
 
 class BatchConfig(ctypes.Structure):
-    """dg_batch_config: launch shape of the batched stage kernel."""
+    """dg_batch_config: launch shape of the batched stage kernels."""
     _fields_ = [("waves_per_block", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("order", ctypes.c_int),
-                ("xcd_chunks", ctypes.c_int)]
+                ("xcd_chunks", ctypes.c_int), ("per_order", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -451,8 +451,8 @@ class Batch:
         _check(lib().dg_batch_bind(self._h, qa, wa, _dev_ptr(dt)))
         self._bound = (list(qs), list(works), dt)
 
-    def set_config(self, waves_per_block=4, blocks_per_cu=2, order=0, xcd_chunks=0):
-        c = BatchConfig(waves_per_block, blocks_per_cu, order, xcd_chunks)
+    def set_config(self, waves_per_block=4, blocks_per_cu=2, order=0, xcd_chunks=0, per_order=1):
+        c = BatchConfig(waves_per_block, blocks_per_cu, order, xcd_chunks, per_order)
         _check(lib().dg_batch_set_config(self._h, ctypes.byref(c)))
 
     def get_config(self) -> dict:

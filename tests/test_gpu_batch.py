@@ -2,10 +2,11 @@
 
 Bar: every mesh of a batch after batched LSRK steps is bitwise the state the
 single-mesh step gives it at the same precision and time step, for every
-launch shape, with and without the captured graph (whose six kernel nodes
-are five stages and one copy: one launch per stage), after tuning; and the
-batched state tracks the oracle's FP64 steps within the reduced-precision
-bar of the single-mesh tests."""
+launch shape of both launch modes, with and without the captured graph
+(whose kernel nodes are five stages and one copy, once in the mixed-order
+mode and once per order present in the per-order mode), after tuning; and
+the batched state tracks the oracle's FP64 steps within the
+reduced-precision bar of the single-mesh tests."""
 import json
 
 import numpy as np
@@ -68,11 +69,13 @@ def _bound(batch, q0, dev, dts):
 
 
 @pytest.mark.parametrize("mode", ["fp32", "split_bf16"])
-def test_batch_equals_single_mesh_bitwise(mode):
+@pytest.mark.parametrize("per_order", [0, 1])
+def test_batch_equals_single_mesh_bitwise(mode, per_order):
     dev, meshes, q0, dts, _ = _problem()
     steps = 3
     ref = _single(meshes, q0, dts, steps, mode, dev)
     b = dg.Batch(meshes, mode)
+    b.set_config(per_order=per_order)
     info = b.info()
     assert info["n_elem"] == sum(6 * n ** 3 for n, _ in SHAPES)
     assert info["n_items"] == sum((6 * n ** 3 + 15) // 16 for n, _ in SHAPES)
@@ -83,16 +86,34 @@ def test_batch_equals_single_mesh_bitwise(mode):
         torch.cuda.synchronize()
         for i, (q, r) in enumerate(zip(qs, ref)):
             assert np.array_equal(q.cpu().numpy(), r), f"mesh {i} (n, p) = {SHAPES[i]} graph={use_graph}"
-    assert b.info()["graph_kernel_nodes"] == 6  # five stages + one copy per step
+    # five stages + one copy per step, per order present (1..4) in the per-order mode
+    assert b.info()["graph_kernel_nodes"] == (24 if per_order else 6)
 
 
-@pytest.mark.parametrize("cfg", [(2, 1, 0, 0), (8, 1, 1, 1), (4, 4, 1, 0), (2, 3, 0, 1)])
+@pytest.mark.parametrize("shapes", [[(3, 2), (4, 2), (3, 2)], [(4, 1), (3, 3)]])
+def test_per_order_mode_with_fewer_orders(shapes):
+    """One order (no stream fork) and two orders (one side stream)."""
+    dev, meshes, q0, dts, _ = _problem(shapes=shapes, seed=83)
+    ref = _single(meshes, q0, dts, 2, "split_bf16", dev)
+    b = dg.Batch(meshes, "split_bf16")
+    assert b.get_config()["per_order"] == 1
+    qs, _, _ = _bound(b, q0, dev, dts)
+    b.rk_step(use_graph=False)
+    b.rk_step(use_graph=True)
+    torch.cuda.synchronize()
+    for q, r in zip(qs, ref):
+        assert np.array_equal(q.cpu().numpy(), r)
+    assert b.info()["graph_kernel_nodes"] == 6 * len({p for _, p in shapes})
+
+
+@pytest.mark.parametrize("cfg", [(2, 1, 0, 0, 0), (8, 1, 1, 1, 0), (4, 4, 1, 0, 0), (2, 3, 0, 1, 0), (2, 1, 1, 1, 1)])
 def test_every_launch_shape_gives_the_same_bits(cfg):
     dev, meshes, q0, dts, _ = _problem(seed=78)
     ref = _single(meshes, q0, dts, 2, "fp32", dev)
     b = dg.Batch(meshes, "fp32")
     b.set_config(*cfg)
-    assert b.get_config() == dict(waves_per_block=cfg[0], blocks_per_cu=cfg[1], order=cfg[2], xcd_chunks=cfg[3])
+    assert b.get_config() == dict(waves_per_block=cfg[0], blocks_per_cu=cfg[1], order=cfg[2], xcd_chunks=cfg[3],
+                                  per_order=cfg[4])
     qs, _, _ = _bound(b, q0, dev, dts)
     for _ in range(2):
         b.rk_step(use_graph=True)
@@ -186,10 +207,12 @@ def test_batch_error_paths():
         b.set_config(3, 1, 0, 0)
     with pytest.raises(dg.DGError):
         b.set_config(4, 5, 0, 0)
+    with pytest.raises(dg.DGError, match="per_order"):
+        b.set_config(4, 2, 0, 0, 2)
     qs = [torch.from_numpy(q).to(dev) for q in q0]
     big = [torch.empty(3 * q.numel(), dtype=torch.float64, device=dev) for q in qs]
     overl = [w[q.numel() // 2:] for w, q in zip(big, qs)]  # work overlapping its q
     fake_q = [w[: q.numel()].view(q.shape) for w, q in zip(big, qs)]
     with pytest.raises(dg.DGError, match="overlaps"):
         b.bind(fake_q, overl, torch.tensor(dts, dtype=torch.float64, device=dev))
-    assert b.get_config() == dict(waves_per_block=4, blocks_per_cu=2, order=0, xcd_chunks=0)
+    assert b.get_config() == dict(waves_per_block=4, blocks_per_cu=2, order=0, xcd_chunks=0, per_order=1)
