@@ -176,6 +176,20 @@ def batched_leg(dg, wl, dev, stream, steps):
         e1.record(stream)
         stream.synchronize()
         ms_graph = e0.elapsed_time(e1) / steps
+        # each launch mode at its default shape, for the record
+        mode_ms = {}
+        for name, c in (("mixed_4x2", (4, 2, 0, 0, 0)), ("per_order_forked", (4, 2, 0, 0, 1)),
+                        ("per_order_serial", (4, 2, 0, 0, 2))):
+            batch.set_config(*c)
+            batch.rk_step(use_graph=True, stream=stream)
+            e0.record(stream)
+            for _ in range(steps):
+                batch.rk_step(use_graph=True, stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+            mode_ms[name] = round(e0.elapsed_time(e1) / steps, 4)
+        batch.set_config(**cfg)
+        batch.rk_step(use_graph=True, stream=stream)
         for m, q, w, d in zip(meshes, qs, works, dts):
             dg.rk_step(m, q, w, 0.0, d, "fp32", stream=stream)
         stream.synchronize()
@@ -196,8 +210,9 @@ def batched_leg(dg, wl, dev, stream, steps):
            "ms_per_step": round(ms_graph, 4), "separate_ms_per_step": round(ms_sep, 4),
            "separate_launches_per_step": 6 * len(meshes),
            "speedup_vs_separate": round(ms_sep / ms_graph, 3),
-           "launches_per_stage": info["graph_kernel_nodes"] // 6,
-           "graph_kernel_nodes_per_step": info["graph_kernel_nodes"], "autotuned": cfg,
+           "launches_per_stage": (info["graph_kernel_nodes"] - 1) // 5 if cfg["per_order"] != 1
+           else info["graph_kernel_nodes"] // 6,
+           "graph_kernel_nodes_per_step": info["graph_kernel_nodes"], "autotuned": cfg, "mode_ms_per_step": mode_ms,
            "autotune_best_ms": round(tune_ms, 4), "steps": steps, "state_finite": finite,
            "host_setup_s": round(setup_s, 1)}
     batch.close()

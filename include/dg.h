@@ -257,9 +257,9 @@ dg_status dg_ns_rk_step(dg_mesh m, const dg_params* prm, double* q, double* T, d
  * size with a few kernel launches per Runge-Kutta stage: a work list holds
  * one item per (mesh, 16-element tile) of every mesh.  In the mixed mode one
  * persistent kernel per stage walks the whole list, running each item with
- * its mesh's order; in the per-order mode one kernel per order present and
- * stage walks that order's items, the chains of different orders running
- * concurrently on forked streams.  This is the launch counterpart of
+ * its mesh's order; in the per-order modes one kernel per order present and
+ * stage walks that order's items (the chains of different orders either
+ * concurrent on forked streams, or in sequence on one stream).  This is the launch counterpart of
  * concatenating independent calls into one larger call (Sec. 4.2,
  * "Concatenation of Function Calls"), aimed at the per-launch floor that
  * small meshes hit (Sec. 5.2, MIRGE-Com vs. MFEM).  Each mesh's result is
@@ -279,9 +279,12 @@ typedef struct {
   int order;           /* work-list order: 0 = highest order first, 1 = mesh order */
   int xcd_chunks;      /* 1 = each of the 8 XCDs walks a contiguous eighth of the
                           list, 0 = the whole grid strides over the list */
-  int per_order;       /* 1 = per-order launches (the four fields above are
-                          then unused: each order's kernel has its own fixed
-                          shape), 0 = one mixed-order launch per stage */
+  int per_order;       /* 0 = one mixed-order launch per stage; 1 = one
+                          launch per order present and stage, each order's
+                          chain on a stream of its own (forked and joined);
+                          2 = the same launches on one stream, stage by
+                          stage.  With 1 or 2 the four fields above are
+                          unused: each order's kernel has its own fixed shape */
 } dg_batch_config;
 
 /* Meshes (n >= 1, all on the same device, not freed while the batch lives)
@@ -298,16 +301,16 @@ dg_status dg_batch_bind(dg_batch b, double* const* q, double* const* work, const
 dg_status dg_batch_set_config(dg_batch b, const dg_batch_config* cfg);
 dg_status dg_batch_get_config(dg_batch b, dg_batch_config* cfg);
 /* One LSRK(5,4) step of every bound mesh: five stage launches and one copy
- * launch (per order present in the per-order mode).  use_graph != 0 replays
+ * launch (per order present in the per-order modes).  use_graph != 0 replays
  * a graph of those launches on `stream`, capturing it first when none
  * matches the current binding, configuration and gamma; use_graph == 0
  * launches them directly (forking to the batch's own streams and joining
- * back into `stream` in the per-order mode). */
+ * back into `stream` when per_order == 1). */
 dg_status dg_batch_rk_step(dg_batch b, const dg_params* prm, int use_graph, hipStream_t stream);
 /* Work items, total elements, and kernel nodes of the captured graph (0 when
  * none is held).  Any pointer may be NULL. */
 dg_status dg_batch_info(dg_batch b, int64_t* n_items, int64_t* n_elem, int* graph_kernel_nodes);
-/* Time every candidate launch shape (the per-order mode, and the mixed mode
+/* Time every candidate launch shape (both per-order modes, and the mixed mode
  * at waves_per_block x blocks_per_cu x order x xcd_chunks) with `trials`
  * steps each after one warm-up step on the bound
  * buffers, keep the fastest and set it.  The bound q are saved before and

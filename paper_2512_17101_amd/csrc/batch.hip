@@ -40,7 +40,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2))) v
   }
   __syncthreads();
 
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
   int64_t begin, end, first, stride;
   if (L.xcd_chunks) {
     const int xcd = blockIdx.x % kXcds;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P < 4 ? 3 :
   for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nb[i] = L.tabs.nb[P][i];
   for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fm[i] = L.tabs.fm[P][i];
   __syncthreads();
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
   const int64_t i = L.p_begin[P] + static_cast<int64_t>(blockIdx.x) * W + wave;
   if (i >= L.p_end[P]) return;
   const BatchItem it = L.items[i];

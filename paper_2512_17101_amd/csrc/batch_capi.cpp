@@ -73,7 +73,7 @@ bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0
 bool valid_config(const dg_batch_config& c) {
   return (c.waves_per_block == 2 || c.waves_per_block == 4 || c.waves_per_block == 8) && c.blocks_per_cu >= 1 &&
          c.blocks_per_cu <= kMaxBlocksPerCu && (c.order == 0 || c.order == 1) &&
-         (c.xcd_chunks == 0 || c.xcd_chunks == 1) && (c.per_order == 0 || c.per_order == 1);
+         (c.xcd_chunks == 0 || c.xcd_chunks == 1) && c.per_order >= 0 && c.per_order <= 2;
 }
 
 // Resolves a configuration into a launch: grid size from the CU count, the
@@ -104,9 +104,11 @@ dg_status make_launch(const dg_batch_s& b, const dg_batch_config& c, double gamm
 }
 
 // The launches of one step: five fused stages (q -> tmp -> q ... ending in
-// tmp) and the copy back to q.  In the per-order mode each order present has
-// its own chain of six launches; the first runs on s, the others on the
-// batch's side streams, forked from s and joined back into it.
+// tmp) and the copy back to q.  In the per-order modes each stage is one
+// launch per order present: with per_order == 1 each order's chain of five
+// stages and its copy runs on a stream of its own (the first on s, the others
+// on the batch's side streams, forked from s and joined back into it); with
+// per_order == 2 everything runs on s, stage by stage, and one copy follows.
 dg_status enqueue_step(const dg_batch_s& b, const dg_batch_config& c, double gamma, hipStream_t s) {
   BatchLaunch L;
   dg_status st = make_launch(b, c, gamma, L);
@@ -121,6 +123,14 @@ dg_status enqueue_step(const dg_batch_s& b, const dg_batch_config& c, double gam
   std::vector<int> orders;
   for (int p = 4; p >= 1; --p)
     if (b.p_end[p] > b.p_begin[p]) orders.push_back(p);
+  if (c.per_order == 2) {
+    for (int k = 0; k < 5; ++k)
+      for (int p : orders) {
+        st = launch_batch_order_stage(b.prec, L, p, kLsrkA[k], kLsrkB[k], k & 1, s);
+        if (st != DG_OK) return st;
+      }
+    return launch_batch_copy(L, 0, L.n_items, s);
+  }
   if (orders.size() > 1) {
     DG_HIP(hipEventRecord(b.fork_ev, s));
     for (size_t j = 1; j < orders.size(); ++j) DG_HIP(hipStreamWaitEvent(b.side[j - 1], b.fork_ev, 0));
@@ -170,7 +180,8 @@ bool same_cfg(const dg_batch_config& a, const dg_batch_config& c) {
 dg_status set_config(dg_batch_s& b, const dg_batch_config& c) {
   if (!valid_config(c))
     return fail(DG_ERR_ARG,
-                "dg_batch: waves_per_block in {2,4,8}, blocks_per_cu in 1..4, order, xcd_chunks and per_order in {0,1}");
+                "dg_batch: waves_per_block in {2,4,8}, blocks_per_cu in 1..4, order and xcd_chunks in {0,1}, "
+                "per_order in {0,1,2}");
   const dg_status st = batch_prepare(b.prec, c.waves_per_block, b.tabs.lds_bytes);
   if (st != DG_OK) return st;
   b.cfg = c;
@@ -506,7 +517,7 @@ extern "C" dg_status dg_batch_autotune(dg_batch b, const dg_params* prm, const c
   dg_batch_config best = prev;
   double best_t = -1.0;
   dg_status st = DG_OK;
-  std::vector<dg_batch_config> cands{dg_batch_config{4, 2, 0, 0, 1}};
+  std::vector<dg_batch_config> cands{dg_batch_config{4, 2, 0, 0, 1}, dg_batch_config{4, 2, 0, 0, 2}};
   for (int w : {2, 4, 8}) {
     const int occ = batch_stage_occupancy(b->prec, w, b->tabs.lds_bytes);
     for (int bp = 1; bp <= std::min(occ, kMaxBlocksPerCu); ++bp)  // more than occ: the same grid as the cap

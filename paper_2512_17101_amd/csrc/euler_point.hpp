@@ -83,17 +83,109 @@ __device__ inline void lf_jump(const double qm[5], const double qp[5], double Nx
   D[4] = 0.5 * ((qm[4] + pm) * Unm - (qp[4] + pp) * Unp) - 0.5 * lamFs * (qm[4] - qp[4]);
 }
 
-// Output of one RHS entry: stored as is, or pushed through the 2N-storage
-// Runge-Kutta stage  res <- a res + dt rhs;  q_out <- q + b res.
-template <bool FUSED>
-__device__ inline void emit(int64_t idx, double val, double* __restrict__ rhs, double* __restrict__ res,
-                            double* __restrict__ qout, const double* __restrict__ q, double a, double b, double dt) {
-  if (!FUSED) {
-    rhs[idx] = val;
+// Values per lane in one round of a tile's loads (at most 25 doubles per
+// lane in flight: one round up to p = 3, three at p = 4).
+template <int TQ>
+constexpr int tile_round_fields() {
+  constexpr int KN = (TQ + 63) / 64;
+  return 25 / KN >= 5 ? 5 : (25 / KN >= 1 ? 25 / KN : 1);
+}
+
+// Copies one tile's state (field f's nval valid values at q + f Es + base)
+// into this wave's LDS buffer (field f at sq[f TQ]), lane l taking entries
+// 64 k + l (coalesced).  The loads are unconditional at indices clamped into
+// the tile (nval >= 1), so a round's loads are all in flight together before
+// its guarded LDS writes; a guarded load would be waited for one by one.
+template <int TQ>
+__device__ inline void stage_tile(double* sq, const double* __restrict__ q, int64_t Es, int64_t base, int nval,
+                                  int lane) {
+  constexpr int KN = (TQ + 63) / 64;
+  constexpr int FG = tile_round_fields<TQ>();
+#pragma unroll
+  for (int f0 = 0; f0 < 5; f0 += FG) {
+    double v[FG][KN];
+#pragma unroll
+    for (int ff = 0; ff < FG; ++ff)
+#pragma unroll
+      for (int k = 0; k < KN; ++k) {
+        const int i = 64 * k + lane;
+        v[ff][k] = f0 + ff < 5 ? q[(f0 + ff) * Es + base + (i < nval ? i : nval - 1)] : 0.0;
+      }
+#pragma unroll
+    for (int ff = 0; ff < FG; ++ff)
+#pragma unroll
+      for (int k = 0; k < KN; ++k) {
+        const int i = 64 * k + lane;
+        if (f0 + ff < 5 && i < nval) sq[(f0 + ff) * TQ + i] = v[ff][k];
+      }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One entry of the fused 2N-storage Runge-Kutta stage
+//   res <- a res + dt rhs;  q_out <- q + b res
+// from values of res and q loaded beforehand (res_old is not used when
+// a == 0: the first stage's residual buffer may hold anything).
+__device__ inline void stage_store(int64_t idx, double val, double res_old, double q_old, double* __restrict__ res,
+                                   double* __restrict__ qout, double a, double b, double dt) {
+  const double r = (a == 0.0 ? 0.0 : a * res_old) + dt * val;
+  res[idx] = r;
+  qout[idx] = q_old + b * r;
+}
+
+// Writes one tile's outputs staged in this wave's LDS buffer (field f's
+// nval valid values at sq[f TQ ..], element-major as in memory from entry
+// base = e0 Np on) to memory, lane l taking entries 64 k + l of each field,
+// so every field leaves with coalesced stores.  In the fused stage every res
+// and q value of a round of fields is loaded before the round's first
+// store: the compiler cannot rule out that a store to res or qout aliases a
+// later load, so entry-by-entry code would wait out one memory latency per
+// entry.
+template <bool FUSED, int TQ>
+__device__ inline void store_tile(const double* sq, int nval, int64_t base, int64_t Es, int lane,
+                                  double* __restrict__ rhs, double* __restrict__ res, double* __restrict__ qout,
+                                  const double* __restrict__ q, double a, double b, double dt) {
+  constexpr int KN = (TQ + 63) / 64;
+  constexpr int FG = tile_round_fields<TQ>();
+  // an opaque copy of the tile offset: otherwise the compiler shares these
+  // addresses with the staging loads at the kernel start and keeps them
+  // live (spilled) across the whole tile
+  {
+    int lo = static_cast<int>(base), hi = static_cast<int>(base >> 32);
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    base = (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
+  }
+  if constexpr (!FUSED) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+      for (int k = 0; k < KN; ++k) {
+        const int i = 64 * k + lane;
+        if (i < nval) rhs[f * Es + base + i] = sq[f * TQ + i];
+      }
   } else {
-    const double r = (a == 0.0 ? 0.0 : a * res[idx]) + dt * val;
-    res[idx] = r;
-    qout[idx] = q[idx] + b * r;
+#pragma unroll
+    for (int f0 = 0; f0 < 5; f0 += FG) {
+      double rv[FG][KN], qv[FG][KN];
+#pragma unroll
+      for (int ff = 0; ff < FG; ++ff)
+#pragma unroll
+        for (int k = 0; k < KN; ++k) {
+          const int i = 64 * k + lane;
+          const bool ok = f0 + ff < 5;  // known at compile time
+          const int64_t idx = (f0 + ff) * Es + base + (i < nval ? i : nval - 1);  // clamped: unconditional loads
+          rv[ff][k] = ok && a != 0.0 ? res[idx] : 0.0;
+          qv[ff][k] = ok ? q[idx] : 0.0;
+        }
+#pragma unroll
+      for (int ff = 0; ff < FG; ++ff)
+#pragma unroll
+        for (int k = 0; k < KN; ++k) {
+          const int i = 64 * k + lane;
+          if (f0 + ff < 5 && i < nval)
+            stage_store((f0 + ff) * Es + base + i, sq[(f0 + ff) * TQ + i], rv[ff][k], qv[ff][k], res, qout, a, b, dt);
+        }
+    }
   }
 }
 

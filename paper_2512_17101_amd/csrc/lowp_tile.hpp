@@ -115,19 +115,8 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
   const double* __restrict__ q = A.q;
   const double gm1 = A.gamma - 1.0;
   const int64_t e0 = tile * 16;
-  if constexpr (STAGED) {
-    const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      const double* src = q + f * Es + e0 * C::NP;
-#pragma unroll
-      for (int k = 0; k < (TQ + 63) / 64; ++k) {
-        const int i = 64 * k + lane;
-        if (i < nval) sq[f * TQ + i] = src[i];
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
+  const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
+  if constexpr (STAGED) stage_tile<TQ>(sq, q, Es, e0 * C::NP, nval, lane);
   {
     const int64_t e = e0 + n;
     const bool valid = e < A.E;
@@ -288,18 +277,60 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
     }
 
     // store: lane (n, g) register v holds row 16 rb + 4 g + v
-    if (valid) {
+    if constexpr (STAGED) {
+      // through the LDS tile buffer (the state is no longer needed there):
+      // coalesced stores, and in the fused stage all res / q loads of a
+      // round in flight together
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
 #pragma unroll
-      for (int f = 0; f < 5; ++f)
+        for (int f = 0; f < 5; ++f)
+#pragma unroll
+          for (int rb = 0; rb < C::NR; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = 16 * rb + 4 * g + v;
+              if (row < C::NP) sq[f * TQ + n * C::NP + row] = static_cast<double>(acc[f][rb][v]);
+            }
+      }
+      __builtin_amdgcn_wave_barrier();
+      store_tile<FUSED, TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
+    } else if constexpr (!FUSED) {
+      if (valid) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f)
+#pragma unroll
+          for (int rb = 0; rb < C::NR; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = 16 * rb + 4 * g + v;
+              if (row < C::NP) A.rhs[f * Es + e * C::NP + row] = static_cast<double>(acc[f][rb][v]);
+            }
+      }
+    } else if (valid) {
+      // one field per round: its res and q loads all issued before its stores
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        double rv[C::NR][4], qv[C::NR][4];
+#pragma unroll
+        for (int rb = 0; rb < C::NR; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * rb + 4 * g + v;
+            const int64_t idx = f * Es + e * C::NP + (row < C::NP ? row : C::NP - 1);  // clamped: unconditional
+            rv[rb][v] = A.a != 0.0 ? A.res[idx] : 0.0;
+            qv[rb][v] = q[idx];
+          }
 #pragma unroll
         for (int rb = 0; rb < C::NR; ++rb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = 16 * rb + 4 * g + v;
             if (row < C::NP)
-              emit<FUSED>(f * Es + e * C::NP + row, static_cast<double>(acc[f][rb][v]), A.rhs, A.res, A.qout, q,
-                          A.a, A.b, A.dt);
+              stage_store(f * Es + e * C::NP + row, static_cast<double>(acc[f][rb][v]), rv[rb][v], qv[rb][v], A.res,
+                          A.qout, A.a, A.b, A.dt);
           }
+      }
     }
   }
 }

@@ -29,24 +29,48 @@ union Pack8 {
   uint16_t u[8];
 };
 
+union Op8 {
+  v8bf v;
+  int w[4];
+};
+
 __device__ inline v8bf tile_operand(const uint16_t* __restrict__ tiles, int t, int lane) {
   return *reinterpret_cast<const v8bf*>(tiles + (static_cast<int64_t>(t) * 64 + lane) * 8);
 }
 
 __device__ inline float bf16_to_float(__bf16 x) { return static_cast<float>(x); }
 
-// Standardised features of state column c (ld = field stride).
-__device__ inline void state_features(const double* __restrict__ q, int64_t ld, int64_t c, const MlpNorm& nm,
-                                      float x[kMlpIn]) {
-  const double rho = q[c];
-  const double ir = 1.0 / rho;
+// Thermodynamic point of state column c (ld = field stride): density, its
+// reciprocal, specific internal energy and mass fractions.
+struct StatePoint {
+  double rho, ir, e, Y[7];
+};
+
+__device__ inline StatePoint state_point(const double* __restrict__ q, int64_t ld, int64_t c) {
+  StatePoint s;
+  s.rho = q[c];
+  s.ir = 1.0 / s.rho;
   const double mx = q[ld + c], my = q[2 * ld + c], mz = q[3 * ld + c];
+  s.e = q[4 * ld + c] * s.ir - 0.5 * (mx * mx + my * my + mz * mz) * s.ir * s.ir;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) s.Y[k] = q[(5 + k) * ld + c] * s.ir;
+  return s;
+}
+
+// Standardised features of a state point.
+__device__ inline void point_features(const StatePoint& s, const MlpNorm& nm, float x[kMlpIn]) {
   double raw[kMlpIn];
-  raw[0] = log(rho);
-  raw[1] = q[4 * ld + c] * ir - 0.5 * (mx * mx + my * my + mz * mz) * ir * ir;
-  for (int k = 0; k < 7; ++k) raw[2 + k] = q[(5 + k) * ld + c] * ir;
+  raw[0] = static_cast<double>(logf(static_cast<float>(s.rho)));  // rounded to BF16 after standardising
+  raw[1] = s.e;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) raw[2 + k] = s.Y[k];
 #pragma unroll
   for (int k = 0; k < kMlpIn; ++k) x[k] = static_cast<float>((raw[k] - nm.mean[k]) * nm.inv_std[k]);
+}
+
+__device__ inline void state_features(const double* __restrict__ q, int64_t ld, int64_t c, const MlpNorm& nm,
+                                      float x[kMlpIn]) {
+  point_features(state_point(q, ld, c), nm, x);
 }
 
 // B operand of layer 1: lane group g supplies features 8 g .. 8 g + 7.
@@ -75,6 +99,21 @@ __device__ inline v8bf hidden_operand(const float (&val)[4][4], int ks) {
   return p.v;
 }
 
+// tanh in FP32 from the hardware base-2 exponential and reciprocal:
+// tanh(x) = 1 - 2 / (2^(a) + 1) with a = 2 x log2(e), which saturates to +-1
+// for large |x|.  Absolute error a few 1e-7 (the 1 - 2r cancellation near 0
+// included), far inside the BF16 rounding that every activation gets next;
+// inference is bound by these vector instructions, two of them
+// transcendental, so the library tanhf, an IEEE division or a separate
+// small-argument branch would cost several times more.
+constexpr float kTanhScale = 2.8853900817779268f;  // 2 log2(e)
+
+__device__ inline float tanh_of_scaled(float a) {
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(a) + 1.0f), 1.0f);
+}
+
+__device__ inline float tanh_fast(float x) { return tanh_of_scaled(x * kTanhScale); }
+
 // Hidden layer: h = bf16(tanh(W x + b)) kept as FP32 values of the BF16 results.
 __device__ inline void hidden_layer(const MlpView& V, int tile0, int nks, const v8bf* B, int bias_off, int g,
                                     float (&h)[4][4]) {
@@ -86,7 +125,7 @@ __device__ inline void hidden_layer(const MlpView& V, int tile0, int nks, const 
                                                   B[ks], z, 0, 0, 0);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float t = tanhf(z[v] + V.master[bias_off + 16 * rb + 4 * g + v]);
+      const float t = tanh_fast(z[v] + V.master[bias_off + 16 * rb + 4 * g + v]);
       h[rb][v] = bf16_to_float(static_cast<__bf16>(t));
     }
   }
@@ -114,19 +153,78 @@ __device__ inline float mlp_forward(const MlpView& V, const float x[kMlpIn], int
   return z[0] + V.master[kOffB4];  // row 0 of the output tile: lane group 0, register 0
 }
 
+// Forward operands and biases of the network held in registers by a wave
+// that evaluates many 16-sample tiles (inference): 22 weight tiles (88 VGPRs)
+// and the 49 bias values its lanes need, loaded once instead of per tile.
+struct FwdWeights {
+  v8bf t[kFwdTiles];
+  float b[3][4][4];  // hidden-layer biases of units 16 rb + 4 g + v, times kTanhScale
+  float b4;
+};
+
+__device__ inline void load_fwd_weights(const MlpView& V, int g, FwdWeights& W) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < kFwdTiles; ++t) W.t[t] = tile_operand(V.fwd, t, lane);
+  const int off[3] = {kOffB1, kOffB2, kOffB3};
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W.b[l][rb][v] = V.master[off[l] + 16 * rb + 4 * g + v] * kTanhScale;
+  W.b4 = V.master[kOffB4];
+}
+
+// hidden_layer with operands from registers, the bias folded into the
+// scaled tanh argument, and the BF16 activations packed straight into the
+// next product's B operands (out[ks] as hidden_operand builds them).
+__device__ inline void hidden_layer_regs(const FwdWeights& W, int tile0, int nks, const v8bf* B, int l,
+                                         v8bf (&out)[2]) {
+  Pack8 p[2];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    v4f z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < nks; ++ks) z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.t[tile0 + rb * nks + ks], B[ks], z, 0, 0, 0);
+    float t[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = tanh_of_scaled(fmaf(z[v], kTanhScale, W.b[l][rb][v]));
+    p[rb >> 1].h[2 * (rb & 1)] = __builtin_convertvector((v2f{t[0], t[1]}), v2bf);
+    p[rb >> 1].h[2 * (rb & 1) + 1] = __builtin_convertvector((v2f{t[2], t[3]}), v2bf);
+  }
+  out[0] = p[0].v;
+  out[1] = p[1].v;
+}
+
+// Forward pass for inference (activations not kept), from the lane's layer-1
+// operand (input_operand of its sample and lane group).
+__device__ inline float mlp_forward_regs(const FwdWeights& W, v8bf in) {
+  v8bf B[2];
+  B[0] = in;
+  hidden_layer_regs(W, kFwdT1, 1, B, 0, B);
+  hidden_layer_regs(W, kFwdT2, 2, B, 1, B);
+  hidden_layer_regs(W, kFwdT3, 2, B, 2, B);
+  v4f z = {0.f, 0.f, 0.f, 0.f};
+  z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.t[kFwdT4 + 0], B[0], z, 0, 0, 0);
+  z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.t[kFwdT4 + 1], B[1], z, 0, 0, 0);
+  return z[0] + W.b4;
+}
+
 __global__ __launch_bounds__(256) void mlp_predict_kernel(MlpView V, int64_t n, int64_t ld,
                                                           const double* __restrict__ q, double* __restrict__ T) {
   const int lane = threadIdx.x & 63;
   const int ln = lane & 15, g = lane >> 4;
   const int64_t tiles = (n + 15) / 16;
+  FwdWeights W;
+  load_fwd_weights(V, g, W);
   for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); tile < tiles;
        tile += static_cast<int64_t>(gridDim.x) * 4) {
     const int64_t i = tile * 16 + ln;
     const int64_t c = i < n ? i : n - 1;
     float x[kMlpIn];
     state_features(q, ld, c, V.norm, x);
-    float h1[4][4], h2[4][4], h3[4][4];
-    const float out = mlp_forward(V, x, g, h1, h2, h3);
+    const float out = mlp_forward_regs(W, input_operand(x, g));
     if (g == 0 && i < n) T[i] = static_cast<double>(out) * V.norm.T_std + V.norm.T_mean;
   }
 }
@@ -307,28 +405,41 @@ __global__ __launch_bounds__(256) void temperature_learned_kernel(ThermoTable th
   const int lane = threadIdx.x & 63;
   const int ln = lane & 15, g = lane >> 4;
   const int64_t groups = (n + 63) / 64;
+  FwdWeights W;
+  load_fwd_weights(V, g, W);
   for (int64_t grp = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6); grp < groups;
        grp += static_cast<int64_t>(gridDim.x) * 4) {
+    // each lane reads and featurises its own point once; the 16 samples of
+    // sub-tile sub reach the layer-1 operand lanes (n, g) by lane shuffles
+    // (group 0: features 0..7, group 1: feature 8, groups 2, 3: zero padding)
+    const int64_t i = grp * 64 + lane;
+    const StatePoint sp = state_point(q, n, i < n ? i : n - 1);
+    float x[kMlpIn];
+    point_features(sp, V.norm, x);
+    Op8 f0, f1;
+    f0.v = input_operand(x, 0);
+    f1.v = input_operand(x, 1);
     float pred = 0.f;
+#pragma unroll
     for (int sub = 0; sub < 4; ++sub) {
-      const int64_t i = grp * 64 + sub * 16 + ln;
-      const int64_t c = i < n ? i : n - 1;
-      float x[kMlpIn];
-      state_features(q, n, c, V.norm, x);
-      float h1[4][4], h2[4][4], h3[4][4];
-      const float out = mlp_forward(V, x, g, h1, h2, h3);
+      const int src = 16 * sub + ln;
+      Op8 in;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int v = __shfl(f0.w[w], src, 64);
+        in.w[w] = g == 0 ? v : 0;
+      }
+      const int v8 = __shfl(f1.w[0], src, 64);
+      if (g == 1) in.w[0] = v8;
+      const float out = mlp_forward_regs(W, in.v);
       const float mine = __shfl(out, ln, 64);
       if (g == sub) pred = mine;
     }
-    const int64_t i = grp * 64 + lane;
     if (i >= n) continue;
-    const double rho = q[i];
-    const double ir = 1.0 / rho;
-    const double mx = q[n + i], my = q[2 * n + i], mz = q[3 * n + i];
-    const double e = q[4 * n + i] * ir - 0.5 * (mx * mx + my * my + mz * mz) * ir * ir;
+    const double e = sp.e;
     double Bh[6] = {0, 0, 0, 0, 0, 0}, Bc[5] = {0, 0, 0, 0, 0}, cR = 0.0;
     for (int k = 0; k < th.ns; ++k) {
-      const double cc = q[(5 + k) * n + i] * ir * th.R[k];
+      const double cc = sp.Y[k] * th.R[k];
       cR += cc;
 #pragma unroll
       for (int m = 0; m < 6; ++m) Bh[m] += cc * th.h[k][m];

@@ -291,11 +291,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
 #pragma unroll
     for (int k = 0; k < kNsSpecies; ++k) w[k] = 0.0;
   }
+  if constexpr (!FUSED) {
 #pragma unroll
-  for (int k = 0; k < R::FH; ++k) {
-    const int f = f0 + k;
-    const double val = f >= 5 ? acc[k] + w[f - 5] : acc[k];
-    emit<FUSED>(f * Es + idx, val, A.rhs, A.res, A.qout, A.q, A.a, A.b, A.dt);
+    for (int k = 0; k < R::FH; ++k) {
+      const int f = f0 + k;
+      A.rhs[f * Es + idx] = f >= 5 ? acc[k] + w[f - 5] : acc[k];
+    }
+  } else {
+    // all res and q loads before the first store, so their latencies overlap
+    double rv[R::FH], qv[R::FH];
+#pragma unroll
+    for (int k = 0; k < R::FH; ++k) {
+      const int64_t at = (f0 + k) * Es + idx;
+      rv[k] = A.a != 0.0 ? A.res[at] : 0.0;
+      qv[k] = A.q[at];
+    }
+#pragma unroll
+    for (int k = 0; k < R::FH; ++k) {
+      const int f = f0 + k;
+      stage_store(f * Es + idx, f >= 5 ? acc[k] + w[f - 5] : acc[k], rv[k], qv[k], A.res, A.qout, A.a, A.b, A.dt);
+    }
   }
 }
 

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 4 ? 2 
   const double* __restrict__ op = A.op;
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
   const int tile = blockIdx.x * TL::WAVES + wave;
   if (tile >= A.ntiles) return;  // uniform per wave; no block barrier follows
   const int n = lane & 15, g = lane >> 4;
@@ -99,18 +99,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 4 ? 2 
   double* sq = s_q[wave];
 
   // stage this tile's state (coalesced: each field's tile block is contiguous)
-  {
-    const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      const double* src = q + f * Es + e0 * C::NP;
-#pragma unroll
-      for (int k = 0; k < (TL::TQ + 63) / 64; ++k) {
-        const int i = 64 * k + lane;
-        if (i < nval) sq[f * TL::TQ + i] = src[i];
-      }
-    }
-  }
+  const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
+  stage_tile<TL::TQ>(sq, q, Es, e0 * C::NP, nval, lane);
   double gm[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) gm[c] = A.geo[c * A.Epad + ec];
@@ -222,16 +212,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 4 ? 2 
     }
   }
   __builtin_amdgcn_wave_barrier();
-  {
-    const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
-#pragma unroll
-    for (int f = 0; f < 5; ++f)
-#pragma unroll
-      for (int k = 0; k < (TL::TQ + 63) / 64; ++k) {
-        const int i = 64 * k + lane;
-        if (i < nval) emit<FUSED>(f * Es + e0 * C::NP + i, sq[f * TL::TQ + i], A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
-      }
-  }
+  store_tile<FUSED, TL::TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
 }
 
 template <int P>

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(lowp_wpe<P,
   __syncthreads();
   // the operator table is read from memory (cache-resident): LDS holds the states
   const uint32_t* op = MODE == 1 ? reinterpret_cast<const uint32_t*>(A.op32) : reinterpret_cast<const uint32_t*>(A.opbf);
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
   const int64_t tile = static_cast<int64_t>(blockIdx.x) * W + wave;
   if (tile < A.ntiles) lowp_tile<P, MODE, FUSED, true>(A, op, s_nb, s_fm, tile, s_q[wave]);
 }
