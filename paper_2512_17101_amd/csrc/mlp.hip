@@ -322,26 +322,23 @@ __global__ __launch_bounds__(256) void mlp_fwd_bwd_kernel(MlpView V, int64_t bat
 
 // Weight and bias gradients from the stored activations and deltas:
 // dW_L[i][j] = sum_b bf16(delta_L[i][b]) H_{L-1}[j][b], db_L[i] = sum_b delta_L[i][b].
-// Waves 0..39: 16 x 16 weight tiles (layer 1: 4, layers 2 and 3: 16 each,
-// layer 4: 4); waves 40..43: the biases of layers 1..4.
-__global__ __launch_bounds__(256) void mlp_weight_grad_kernel(int64_t bpad, const uint16_t* __restrict__ H,
-                                                              const float* __restrict__ D, float* __restrict__ grad) {
+// One block per 16 x 16 weight tile (layer 1: 4, layers 2 and 3: 16 each,
+// layer 4: 4); its kGradWaves waves take interleaved k-steps of 32 samples
+// (four k-steps' operands loaded before their products, so the loads overlap)
+// and their partial tiles are summed in LDS in wave order (deterministic).
+// The blocks of column tile 0 also sum their rows' deltas for the biases from
+// the FP32 values they load anyway.
+constexpr int kGradWaves = 8;
+
+__global__ __launch_bounds__(64 * kGradWaves) void mlp_weight_grad_kernel(int64_t bpad, const uint16_t* __restrict__ H,
+                                                                       const float* __restrict__ D,
+                                                                       float* __restrict__ grad) {
+  __shared__ v4f s_acc[kGradWaves][64];
+  __shared__ float s_bias[kGradWaves][64];
   const int lane = threadIdx.x & 63;
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = blockIdx.x;
   const int64_t LH = 64 * bpad;
-  if (w >= 44) return;
-  if (w >= 40) {
-    const int L = w - 40 + 1;  // 1..4
-    const int fo = L == 4 ? 1 : 64;
-    const int off = L == 1 ? kOffB1 : L == 2 ? kOffB2 : L == 3 ? kOffB3 : kOffB4;
-    if (lane < fo) {
-      const float* d = D + (L - 1) * LH + lane * bpad;
-      float s = 0.f;
-      for (int64_t b = 0; b < bpad; ++b) s += d[b];
-      grad[off + lane] = s;
-    }
-    return;
-  }
   int L, rb, cb;
   if (w < 4) { L = 1; rb = w; cb = 0; }
   else if (w < 20) { L = 2; rb = (w - 4) / 4; cb = (w - 4) % 4; }
@@ -349,22 +346,57 @@ __global__ __launch_bounds__(256) void mlp_weight_grad_kernel(int64_t bpad, cons
   else { L = 4; rb = 0; cb = w - 36; }
   const int fo = L == 4 ? 1 : 64, fi = L == 1 ? kMlpIn : 64;
   const int offW = L == 1 ? kOffW1 : L == 2 ? kOffW2 : L == 3 ? kOffW3 : kOffW4;
+  const int offB = L == 1 ? kOffB1 : L == 2 ? kOffB2 : L == 3 ? kOffB3 : kOffB4;
   const int i = lane & 15, g = lane >> 4;
   const float* dA = D + (L - 1) * LH + (16 * rb + i) * bpad;
   const uint16_t* hB = H + (L - 1) * LH + (16 * cb + i) * bpad;
+  const int64_t nks = bpad / 32;
   v4f acc = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t ks = 0; ks < bpad / 32; ++ks) {
-    const int64_t b0 = ks * 32 + 8 * g;
-    Pack8 a;
+  float bsum = 0.f;
+  constexpr int U = 4;
+  for (int64_t ks0 = wave; ks0 < nks; ks0 += U * kGradWaves) {
+    float da[U][8];
+    v8bf bb[U];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) a.h[e] = __builtin_convertvector((v2f{dA[b0 + 2 * e], dA[b0 + 2 * e + 1]}), v2bf);
-    const v8bf bb = *reinterpret_cast<const v8bf*>(hB + b0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, bb, acc, 0, 0, 0);
+    for (int u = 0; u < U; ++u) {
+      const int64_t ks = ks0 + static_cast<int64_t>(u) * kGradWaves;
+      const int64_t b0 = (ks < nks ? ks : nks - 1) * 32 + 8 * g;  // clamped: loads stay unconditional
+#pragma unroll
+      for (int e = 0; e < 8; ++e) da[u][e] = dA[b0 + e];
+      bb[u] = *reinterpret_cast<const v8bf*>(hB + b0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ks0 + static_cast<int64_t>(u) * kGradWaves >= nks) break;
+      Pack8 a;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a.h[e] = __builtin_convertvector((v2f{da[u][2 * e], da[u][2 * e + 1]}), v2bf);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, bb[u], acc, 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bsum += da[u][e];
+    }
+  }
+  s_acc[wave][lane] = acc;
+  s_bias[wave][lane] = bsum;
+  __syncthreads();
+  if (wave != 0) return;
+  v4f t = s_acc[0][lane];
+  float bt = s_bias[0][lane];
+  for (int k = 1; k < kGradWaves; ++k) {
+    t += s_acc[k][lane];
+    bt += s_bias[k][lane];
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = 16 * rb + 4 * g + v, col = 16 * cb + i;
-    if (row < fo && col < fi) grad[offW + row * fi + col] = acc[v];
+    if (row < fo && col < fi) grad[offW + row * fi + col] = t[v];
+  }
+  if (cb == 0) {
+    // row 16 rb + i: its partial sums sit in lanes i, i + 16, i + 32, i + 48 (one per sample group g)
+    const float b1 = __shfl(bt, i, 64), b2 = __shfl(bt, i + 16, 64), b3 = __shfl(bt, i + 32, 64),
+                b4 = __shfl(bt, i + 48, 64);
+    const int row = 16 * rb + i;
+    if (g == 0 && row < fo) grad[offB + row] = (b1 + b2) + (b3 + b4);
   }
 }
 
@@ -536,8 +568,20 @@ dg_status launch_mlp_forward_backward(const MlpView& v, int64_t batch, int64_t b
   return DG_OK;
 }
 
+__global__ void mlp_zero_kernel(float* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+dg_status launch_mlp_zero(float* p, int n, hipStream_t s) {
+  if (n <= 0) return DG_OK;
+  mlp_zero_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
 dg_status launch_mlp_weight_grads(int64_t bpad, const uint16_t* H, const float* D, float* grad, hipStream_t s) {
-  mlp_weight_grad_kernel<<<11, 256, 0, s>>>(bpad, H, D, grad);
+  mlp_weight_grad_kernel<<<40, 64 * kGradWaves, 0, s>>>(bpad, H, D, grad);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

@@ -49,6 +49,7 @@ dg_status launch_mlp_forward_backward(const MlpView& v, int64_t batch, int64_t b
                                       const int64_t* idx, const double* T, uint16_t* H, float* D, float* loss,
                                       hipStream_t s);
 dg_status launch_mlp_weight_grads(int64_t bpad, const uint16_t* H, const float* D, float* grad, hipStream_t s);
+dg_status launch_mlp_zero(float* p, int n, hipStream_t s);
 dg_status launch_mlp_adam(float* master, float* m, float* v, const float* grad, float lr, float b1, float b2,
                           float eps, float c1, float c2, hipStream_t s);
 dg_status launch_mlp_layouts(const float* master, const int32_t* src, uint16_t* dst, int64_t count, hipStream_t s);

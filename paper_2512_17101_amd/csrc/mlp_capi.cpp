@@ -242,7 +242,8 @@ extern "C" dg_status dg_mlp_loss_grad(dg_mlp h, int64_t batch, int64_t ld, const
   const int64_t bpad = (batch + 31) / 32 * 32;
   st = ensure_scratch(h, bpad);
   if (st != DG_OK) return st;
-  DG_HIP(hipMemsetAsync(h->loss, 0, 4, s));
+  st = launch_mlp_zero(h->loss, 1, s);  // a kernel, not a memset node, should the caller capture this
+  if (st != DG_OK) return st;
   st = launch_mlp_forward_backward(view_of(h), batch, bpad, ld, q, idx, T, h->H, h->D, h->loss, s);
   if (st != DG_OK) return st;
   st = launch_mlp_weight_grads(bpad, h->H, h->D, h->grad, s);
