@@ -438,8 +438,12 @@ def main():
         work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
         qs = q.clone()
         for mode in modes:
+            # the step's launch shape (tiles per block, fused or split stages) from the autotuner
+            with torch.cuda.stream(stream):
+                cfg, _ = mesh.autotune(mode, trials=2, stream=stream)
             t_rk = time_rk_step(dg, mesh, qs, work, 1e-4, mode, max(2, args.steps // 10), stream)
             (rec if mode == head else variants[mode])["lsrk_step_ms"] = round(t_rk, 4)
+            (rec if mode == head else variants[mode])["lsrk_launch"] = cfg
         del work, qs
     if args.cpu_sample > 0:
         cpu, idx, ref = cpu_baseline(xyz, vid, q_np, p, args.cpu_sample)

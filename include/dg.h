@@ -121,10 +121,36 @@ dg_status dg_rhs(dg_mesh m, const dg_params* prm, dg_precision prec, const doubl
  * q <- q + b_s res.  q: device [5][E][Np], updated in place.  work: device
  * scratch of at least 2 * 5 * E * Np doubles, caller-owned, contents
  * overwritten.  t is accepted for non-autonomous models (the Euler RHS does
- * not depend on it).  Each stage is one fused launch (RHS + stage update into
- * a second state buffer); a final copy returns the state to q. */
+ * not depend on it).  With the mesh's launch configuration for prec (below)
+ * each stage is one fused launch (RHS + stage update into a second state
+ * buffer, then a final copy returns the state to q) or an RHS launch into
+ * work followed by the pointwise update of q in place; both give the same
+ * bits. */
 dg_status dg_rk_step(dg_mesh m, const dg_params* prm, dg_precision prec, double* q, double* work,
                      double t, double dt, hipStream_t stream);
+
+/* Launch configuration of one mesh's RHS and Runge-Kutta kernels for one
+ * contraction precision.  Results do not depend on it (bitwise). */
+typedef struct {
+  int waves_per_block; /* 16-element tiles per block: 2 or 4 (p = 4: 2 only; a
+                          request of 4 runs 2) */
+  int rk_fused;        /* 1 = fused stage launches, 0 = RHS launch + update */
+} dg_launch_config;
+/* Initial configuration of every precision: {4, 1}.  Set and get are
+ * synchronous host calls that must not overlap calls running on the mesh. */
+dg_status dg_mesh_set_launch(dg_mesh m, dg_precision prec, const dg_launch_config* cfg);
+dg_status dg_mesh_get_launch(dg_mesh m, dg_precision prec, dg_launch_config* cfg);
+/* Times every launch configuration of the mesh at precision prec (`trials`
+ * dg_rk_step calls each after one warm-up, on a uniform state in temporary
+ * device buffers the call allocates and frees), keeps the fastest and sets
+ * it.  With cache_path != NULL the choice is first looked up in that JSON
+ * file under a key of (device architecture, CU count, precision, p, E) and,
+ * when tuned, written back.  chosen (may be NULL) receives the
+ * configuration, best_ms (may be NULL) its time per step, negative when it
+ * came from the cache.  Synchronous on `stream`; must not overlap other calls
+ * on the mesh. */
+dg_status dg_autotune(dg_mesh m, const dg_params* prm, dg_precision prec, const char* cache_path, int trials,
+                      dg_launch_config* chosen, double* best_ms, hipStream_t stream);
 
 /* Pointwise stage update used by unfused stepping:
  *   res <- a * res + dt * rhs;  q <- q + b * res   over n doubles. */

@@ -12,6 +12,7 @@
 
 #include "batch.hpp"
 #include "internal.hpp"
+#include "json_cache.hpp"
 
 using namespace dg;
 
@@ -188,7 +189,6 @@ dg_status set_config(dg_batch_s& b, const dg_batch_config& c) {
   return DG_OK;
 }
 
-// ---- autotuner cache: {"version": 1, "entries": {"<key>": {...}, ...}} ----
 
 std::string cache_key(const dg_batch_s& b) {
   std::vector<std::pair<int, int64_t>> ms;
@@ -212,69 +212,14 @@ std::string cache_key(const dg_batch_s& b) {
   return buf;
 }
 
-// Every "key": {object} pair of the "entries" object, objects kept as text.
-std::map<std::string, std::string> read_cache(const std::string& path) {
-  std::map<std::string, std::string> out;
-  std::ifstream f(path);
-  if (!f) return out;
-  std::stringstream ss;
-  ss << f.rdbuf();
-  const std::string s = ss.str();
-  size_t pos = s.find("\"entries\"");
-  if (pos == std::string::npos) return out;
-  pos = s.find('{', pos);
-  if (pos == std::string::npos) return out;
-  ++pos;
-  for (;;) {
-    const size_t k0 = s.find_first_of("\"}", pos);
-    if (k0 == std::string::npos || s[k0] == '}') break;
-    const size_t k1 = s.find('"', k0 + 1);
-    if (k1 == std::string::npos) break;
-    const size_t o0 = s.find('{', k1);
-    const size_t o1 = o0 == std::string::npos ? o0 : s.find('}', o0);
-    if (o1 == std::string::npos) break;
-    out[s.substr(k0 + 1, k1 - k0 - 1)] = s.substr(o0, o1 - o0 + 1);
-    pos = o1 + 1;
-  }
-  return out;
-}
-
-bool field(const std::string& obj, const char* name, double& v) {
-  const std::string pat = std::string("\"") + name + "\"";
-  const size_t p = obj.find(pat);
-  if (p == std::string::npos) return false;
-  const size_t c = obj.find(':', p + pat.size());
-  if (c == std::string::npos) return false;
-  char* end = nullptr;
-  v = std::strtod(obj.c_str() + c + 1, &end);
-  return end != obj.c_str() + c + 1;
-}
-
 bool parse_entry(const std::string& obj, dg_batch_config& c) {
   double w, bp, o, x, po;
-  if (!field(obj, "waves_per_block", w) || !field(obj, "blocks_per_cu", bp) || !field(obj, "order", o) ||
-      !field(obj, "xcd_chunks", x) || !field(obj, "per_order", po))
+  if (!cache_field(obj, "waves_per_block", w) || !cache_field(obj, "blocks_per_cu", bp) || !cache_field(obj, "order", o) ||
+      !cache_field(obj, "xcd_chunks", x) || !cache_field(obj, "per_order", po))
     return false;
   c = dg_batch_config{static_cast<int>(w), static_cast<int>(bp), static_cast<int>(o), static_cast<int>(x),
                       static_cast<int>(po)};
   return valid_config(c);
-}
-
-bool write_cache(const std::string& path, const std::map<std::string, std::string>& entries) {
-  const std::string tmp = path + ".tmp";
-  {
-    std::ofstream f(tmp);
-    if (!f) return false;
-    f << "{\n  \"version\": 1,\n  \"entries\": {";
-    bool first = true;
-    for (const auto& kv : entries) {
-      f << (first ? "\n" : ",\n") << "    \"" << kv.first << "\": " << kv.second;
-      first = false;
-    }
-    f << "\n  }\n}\n";
-    if (!f) return false;
-  }
-  return std::rename(tmp.c_str(), path.c_str()) == 0;
 }
 
 }  // namespace

@@ -92,6 +92,19 @@ extern "C" dg_status dg_rk_step(dg_mesh h, const dg_params* prm, dg_precision pr
   DeviceGuard g(m.device);
   if (!g.ok) return fail(DG_ERR_HIP, "dg_rk_step: hipSetDevice failed");
   double* res = work;
+  if (!m.launch[prec].rk_fused) {
+    // RHS into work + n, then the pointwise stage update of q in place
+    double* rhs = work + n;
+    for (int s = 0; s < 5; ++s) {
+      st = prec == DG_FP64
+               ? launch_rhs_euler_fp64(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream)
+               : launch_rhs_euler_lowp(m, prec, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+      if (st != DG_OK) return st;
+      st = launch_lsrk_update(static_cast<int64_t>(n), kLsrkA[s], kLsrkB[s], dt, rhs, res, q, stream);
+      if (st != DG_OK) return st;
+    }
+    return DG_OK;
+  }
   double* buf[2] = {q, work + n};
   for (int s = 0; s < 5; ++s) {
     const double* qin = buf[s & 1];

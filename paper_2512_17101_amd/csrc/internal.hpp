@@ -89,6 +89,8 @@ struct Mesh {
   uint16_t* d_opbf = nullptr;     // BF16 hi/lo table (LowpLayout)
   int* d_fmask = nullptr;         // [4][Nfp]
   uint8_t* d_nbtab = nullptr;     // [4][24][Nfp]
+  // launch configuration per contraction precision (dg_precision index)
+  dg_launch_config launch[3] = {{4, 1}, {4, 1}, {4, 1}};
 };
 
 // kernel launchers (defined in the .hip files)
@@ -102,5 +104,7 @@ dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, 
                                 hipStream_t s);
 dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,
                              double* q, hipStream_t s);
+// q[f][n] <- v[f] for f < 5 (a uniform state).
+dg_status launch_fill_state(double* q, int64_t n, const double v[5], hipStream_t s);
 
 }  // namespace dg

@@ -17,7 +17,29 @@ __global__ __launch_bounds__(256) void lsrk_update_kernel(int64_t n, double a, d
   }
 }
 
+struct Five {
+  double v[5];
+};
+
+__global__ __launch_bounds__(256) void fill_state_kernel(double* __restrict__ q, int64_t n, Five v) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+#pragma unroll
+    for (int f = 0; f < 5; ++f) q[f * n + i] = v.v[f];
+}
+
 }  // namespace
+
+dg_status launch_fill_state(double* q, int64_t n, const double v[5], hipStream_t s) {
+  if (n <= 0) return DG_OK;
+  Five f;
+  for (int k = 0; k < 5; ++k) f.v[k] = v[k];
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  fill_state_kernel<<<static_cast<unsigned>(blocks), 256, 0, s>>>(q, n, f);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
 
 dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res, double* q,
                              hipStream_t s) {

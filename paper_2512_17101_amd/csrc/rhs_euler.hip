@@ -55,25 +55,26 @@ struct RhsArgs {
   double gamma, a, b, dt;
 };
 
-// Waves per block: the per-wave state tile lives in LDS (5 fields x 16
-// elements x Np doubles), so order 4 uses two-wave blocks.  The operator
+// Waves (tiles) per block W: the per-wave state tile lives in LDS (5 fields
+// x 16 elements x Np doubles), so order 4 runs two-wave blocks only; up to
+// p = 3 the mesh's launch configuration picks two or four.  The operator
 // table is read from memory (it stays in the L1/L2 caches): keeping it in LDS
 // as well would cap the kernel at two waves per SIMD (measured slower at p = 3
 // than the three waves per SIMD this layout allows).
-template <int P>
+template <int P, int W>
 struct Tiling {
   using C = Cfg<P>;
-  static constexpr int WAVES = P >= 4 ? 2 : 4;
+  static constexpr int WAVES = W;
   static constexpr int TQ = 16 * C::NP;  // doubles of one field of one tile
 };
 
 // Register budget for three waves per SIMD (two at p = 4, whose tile would
 // spill): measured at p = 3, the scheduling
 // this target produces runs 28 % faster than the unconstrained default.
-template <int P, bool FUSED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 4 ? 2 : 3))) void rhs_euler_fp64_kernel(RhsArgs A) {
+template <int P, bool FUSED, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ? 2 : 3))) void rhs_euler_fp64_kernel(RhsArgs A) {
   using C = Cfg<P>;
-  using TL = Tiling<P>;
+  using TL = Tiling<P, W>;
   constexpr int NB16 = C::NB16 > 0 ? C::NB16 : 1;
   constexpr int NB4 = C::NB4 > 0 ? C::NB4 : 1;
   __shared__ double s_q[TL::WAVES][5 * TL::TQ];
@@ -215,14 +216,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 4 ? 2 
   store_tile<FUSED, TL::TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
 }
 
+template <int P, int W>
+void launch_pw(const RhsArgs& args, bool fused, hipStream_t s) {
+  const int blocks = (args.ntiles + W - 1) / W;
+  if (fused)
+    rhs_euler_fp64_kernel<P, true, W><<<blocks, 64 * W, 0, s>>>(args);
+  else
+    rhs_euler_fp64_kernel<P, false, W><<<blocks, 64 * W, 0, s>>>(args);
+}
+
 template <int P>
 dg_status launch_p(const Mesh& m, const RhsArgs& args, bool fused, hipStream_t s) {
-  const int waves = Tiling<P>::WAVES;
-  const int blocks = (args.ntiles + waves - 1) / waves;
-  if (fused)
-    rhs_euler_fp64_kernel<P, true><<<blocks, 64 * waves, 0, s>>>(args);
+  if (P < 4 && m.launch[DG_FP64].waves_per_block == 4)
+    launch_pw<P, P < 4 ? 4 : 2>(args, fused, s);
   else
-    rhs_euler_fp64_kernel<P, false><<<blocks, 64 * waves, 0, s>>>(args);
+    launch_pw<P, 2>(args, fused, s);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

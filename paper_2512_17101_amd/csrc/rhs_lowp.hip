@@ -9,21 +9,17 @@ namespace {
 
 using namespace lowp;
 
-constexpr int kWaves = 4;
-
-// Waves per block (one 16-element tile each; the tile's state is staged in
-// LDS, 5 x 16 Np doubles per wave) and the register target: three waves per
-// SIMD up to p = 3, two at p = 4.
-template <int P>
-constexpr int lowp_waves() { return P >= 4 ? 2 : kWaves; }
+// W waves per block (one 16-element tile each; the tile's state is staged in
+// LDS, 5 x 16 Np doubles per wave: two or four up to p = 3, two at p = 4, as
+// the mesh's launch configuration says) and the register target: three
+// waves per SIMD up to p = 3, two at p = 4.
 template <int P, int MODE>
 constexpr int lowp_wpe() { return P < 4 ? 3 : 2; }
 
-template <int P, int MODE, bool FUSED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(lowp_wpe<P, MODE>()))) void rhs_euler_lowp_kernel(
+template <int P, int MODE, bool FUSED, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lowp_wpe<P, MODE>()))) void rhs_euler_lowp_kernel(
     LowArgs A) {
   using C = LCfg<P>;
-  constexpr int W = lowp_waves<P>();
   __shared__ double s_q[W][5 * 16 * C::NP];
   __shared__ uint8_t s_nb[4 * 24 * C::NFP];
   __shared__ int s_fm[4 * C::NFP];
@@ -37,20 +33,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(lowp_wpe<P,
   if (tile < A.ntiles) lowp_tile<P, MODE, FUSED, true>(A, op, s_nb, s_fm, tile, s_q[wave]);
 }
 
-template <int P, int MODE, bool FUSED>
-int lowp_grid(const Mesh& m) {
-  const int64_t tiles = m.Epad / 16;
-  constexpr int W = lowp_waves<P>();
-  return static_cast<int>((tiles + W - 1) / W);
+template <int P, int MODE, int W>
+void launch_lowp_pw(const Mesh& m, const LowArgs& args, bool fused, hipStream_t s) {
+  const int blocks = static_cast<int>((m.Epad / 16 + W - 1) / W);
+  if (fused)
+    rhs_euler_lowp_kernel<P, MODE, true, W><<<blocks, 64 * W, 0, s>>>(args);
+  else
+    rhs_euler_lowp_kernel<P, MODE, false, W><<<blocks, 64 * W, 0, s>>>(args);
 }
 
 template <int P, int MODE>
 dg_status launch_lowp_p(const Mesh& m, const LowArgs& args, bool fused, hipStream_t s) {
-  constexpr int W = lowp_waves<P>();
-  if (fused)
-    rhs_euler_lowp_kernel<P, MODE, true><<<lowp_grid<P, MODE, true>(m), 64 * W, 0, s>>>(args);
+  if (P < 4 && m.launch[MODE].waves_per_block == 4)
+    launch_lowp_pw<P, MODE, P < 4 ? 4 : 2>(m, args, fused, s);
   else
-    rhs_euler_lowp_kernel<P, MODE, false><<<lowp_grid<P, MODE, false>(m), 64 * W, 0, s>>>(args);
+    launch_lowp_pw<P, MODE, 2>(m, args, fused, s);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

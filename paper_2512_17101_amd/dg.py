@@ -28,13 +28,22 @@ EXPORTS = ("dg_reference_operators", "dg_mesh_create", "dg_mesh_info", "dg_mesh_
            "dg_mlp_fit_normalization", "dg_mlp_loss_grad", "dg_mlp_train_step", "dg_mlp_predict",
            "dg_temperature_learned", "dg_batch_create", "dg_batch_destroy", "dg_batch_bind",
            "dg_batch_set_config", "dg_batch_get_config", "dg_batch_rk_step", "dg_batch_info", "dg_batch_autotune",
-           "dg_ns_rhs", "dg_ns_rk_step", "dg_last_error")
+           "dg_ns_rhs", "dg_ns_rk_step", "dg_mesh_set_launch", "dg_mesh_get_launch", "dg_autotune",
+           "dg_last_error")
 
 
 class DGError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class LaunchConfig(ctypes.Structure):
+    """dg_launch_config: one mesh's RHS / Runge-Kutta launch shape for one precision."""
+    _fields_ = [("waves_per_block", ctypes.c_int), ("rk_fused", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class _Params(ctypes.Structure):
@@ -103,6 +112,10 @@ def lib():
         L.dg_batch_autotune.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_char_p, ctypes.c_int,
                                         ctypes.POINTER(BatchConfig), ctypes.POINTER(_dbl), _c_p]
         L.dg_ns_rhs.argtypes = [_c_p, ctypes.POINTER(_Params), _c_p, _c_p, _c_p, _c_p, _c_p]
+        L.dg_mesh_set_launch.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(LaunchConfig)]
+        L.dg_mesh_get_launch.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(LaunchConfig)]
+        L.dg_autotune.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_int, ctypes.c_char_p, ctypes.c_int,
+                                  ctypes.POINTER(LaunchConfig), ctypes.POINTER(_dbl), _c_p]
         L.dg_ns_rk_step.argtypes = [_c_p, ctypes.POINTER(_Params), _c_p, _c_p, _c_p, _dbl, _dbl, ctypes.c_int, _c_p]
         for name in EXPORTS:
             if name != "dg_last_error":
@@ -177,6 +190,24 @@ class Mesh:
         out = np.zeros((self.E, self.Np, 3))
         _check(lib().dg_mesh_nodes(self._h, _np_ptr(out)))
         return out
+
+    def set_launch(self, mode: str = "fp64", waves_per_block: int = 4, rk_fused: int = 1):
+        c = LaunchConfig(waves_per_block, rk_fused)
+        _check(lib().dg_mesh_set_launch(self._h, PRECISIONS[mode], ctypes.byref(c)))
+
+    def get_launch(self, mode: str = "fp64") -> dict:
+        c = LaunchConfig()
+        _check(lib().dg_mesh_get_launch(self._h, PRECISIONS[mode], ctypes.byref(c)))
+        return c.as_dict()
+
+    def autotune(self, mode: str = "fp64", gamma: float = 1.4, cache_path=None, trials: int = 3, stream=None):
+        """Tune this mesh's launch configuration; returns (config dict, ms per step or -1 from cache)."""
+        prm = _params(gamma)
+        c, ms = LaunchConfig(), _dbl()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(lib().dg_autotune(self._h, ctypes.byref(prm), PRECISIONS[mode], path, int(trials), ctypes.byref(c),
+                                 ctypes.byref(ms), _stream(stream)))
+        return c.as_dict(), ms.value
 
     def face_map(self):
         ne = np.zeros((self.E, 4 * self.Nfp), dtype=np.int64)

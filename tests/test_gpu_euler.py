@@ -218,3 +218,64 @@ def test_error_paths():
     with pytest.raises(dg.DGError) as ei:
         dg.Mesh(5, c["xyz"], c["vid"])
     assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_launch_configurations_give_the_same_bits(p):
+    """Every launch configuration (2 or 4 tiles per block; fused or unfused
+    Runge-Kutta stages) of every contraction precision gives bitwise the
+    right-hand side and the steps of the initial one, on a ragged mesh with
+    jumping traces."""
+    dev = _dev()
+    c = _case(p, (3, 4, 5), pert_seed=2003)
+    q_np = c["q"] * (1.0 + 1e-3 * np.random.default_rng(77).standard_normal(c["q"].shape))
+    mesh = dg.Mesh(p, c["xyz"], c["vid"])
+    q0 = torch.from_numpy(np.ascontiguousarray(q_np)).to(dev)
+    dt = 0.2 * oe.cfl_dt(c["ops"], c["geo"], q_np, 1.0)
+    for mode in ("fp64", "fp32", "split_bf16"):
+        assert mesh.get_launch(mode) == dict(waves_per_block=4, rk_fused=1)
+        ref_rhs, ref_q = None, None
+        for w in (4, 2):
+            for fused in (1, 0):
+                mesh.set_launch(mode, w, fused)
+                out = torch.empty_like(q0)
+                dg.rhs(mesh, q0, out, mode)
+                q = q0.clone()
+                work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
+                for s in range(2):
+                    dg.rk_step(mesh, q, work, s * dt, dt, mode)
+                torch.cuda.synchronize()
+                if ref_rhs is None:
+                    ref_rhs, ref_q = out.clone(), q.clone()
+                assert torch.equal(out, ref_rhs), f"{mode} rhs waves={w}"
+                assert torch.equal(q, ref_q), f"{mode} rk waves={w} fused={fused}"
+        mesh.set_launch(mode, 4, 1)
+
+
+def test_autotune_chooses_sets_and_caches(tmp_path):
+    dev = _dev()
+    c = _case(3, (4, 4, 4))
+    mesh = dg.Mesh(3, c["xyz"], c["vid"])
+    cache = tmp_path / "tune.json"
+    cfg, ms = mesh.autotune("split_bf16", cache_path=cache, trials=2)
+    assert ms > 0 and cfg == mesh.get_launch("split_bf16")
+    assert cfg["waves_per_block"] in (2, 4) and cfg["rk_fused"] in (0, 1)
+    assert mesh.get_launch("fp64") == dict(waves_per_block=4, rk_fused=1)  # other precisions untouched
+    import json
+    (key, entry), = json.loads(cache.read_text())["entries"].items()
+    assert "split_bf16" in key and ":p3:" in key and f":E{mesh.E}" in key
+    assert {k: entry[k] for k in cfg} == cfg
+    mesh2 = dg.Mesh(3, c["xyz"], c["vid"])
+    cfg2, ms2 = mesh2.autotune("split_bf16", cache_path=cache, trials=2)
+    assert cfg2 == cfg and ms2 < 0
+    with pytest.raises(dg.DGError, match="waves_per_block"):
+        mesh.set_launch("fp64", 3, 1)
+    with pytest.raises(dg.DGError, match="trials"):
+        mesh.autotune("fp64", trials=0)
+    # tuned mesh still matches the oracle
+    q = torch.from_numpy(c["q"]).to(dev)
+    out = torch.empty_like(q)
+    mesh.set_launch("fp64", 2, 0)
+    dg.rhs(mesh, q, out)
+    torch.cuda.synchronize()
+    _check(c, out.cpu().numpy(), label="p=3 waves=2")
