@@ -248,7 +248,7 @@ def reacting_leg(dg, wl, dev, stream, steps):
     nn = mesh.E * mesh.Np
     T = torch.empty((mesh.E, mesh.Np), dtype=torch.float64, device=dev)
     it = torch.empty((mesh.E, mesh.Np), dtype=torch.int32, device=dev)
-    sig = torch.empty((33, mesh.E, mesh.Np), dtype=torch.float64, device=dev)
+    sig = torch.empty((mesh.E, mesh.Np, 33), dtype=torch.float64, device=dev)
     out = torch.empty_like(q)
     with torch.cuda.stream(stream):
         dg.temperature(th, q, T, it, stream=stream)

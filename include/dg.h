@@ -250,7 +250,7 @@ dg_status dg_temperature_learned(dg_thermo th, dg_mlp m, int64_t n, const double
  * terms by Bassi & Rebay's first scheme: lifted gradients of
  * v = (u, v, w, T, Y_1 .. Y_7) with the central trace,
  *   sigma_d(v) = sum_a (da/dx_d) D_a v + LIFT( Fscale n_d (v+ - v-) / 2 ),
- * stored as sigma[3 c + d][E][Np]; stress tau = mu (grad u + grad u^T
+ * stored node-major as sigma[E][Np][3 c + d]; stress tau = mu (grad u + grad u^T
  * - 2/3 div u I), heat flux -kappa grad T with kappa = mu cp / Pr, species
  * flux J_k = -(mu / Sc) grad Y_k; viscous flux (0, tau, u.tau + kappa grad T
  * - sum_k h_k J_k, -J_k).  Total flux F = F_inviscid - F_viscous; surface
@@ -263,7 +263,7 @@ dg_status dg_temperature_learned(dg_thermo th, dg_mlp m, int64_t n, const double
  * Errors: DG_ERR_ARG for bad parameters, pointers or aliasing,
  * DG_ERR_UNSUPPORTED for a species count other than 7. */
 
-/* sigma (device [33][E][Np]) receives the lifted gradients; rhs (device
+/* sigma (device [E][Np][33]) receives the lifted gradients; rhs (device
  * [12][E][Np]) the right-hand side.  q, T, sigma and rhs must not overlap. */
 dg_status dg_ns_rhs(dg_mesh m, const dg_params* prm, const double* q, const double* T, double* sigma, double* rhs,
                     hipStream_t stream);

@@ -42,17 +42,35 @@ __device__ inline void load_state(const double* __restrict__ q, int64_t Es, int6
   for (int f = 0; f < kNsFields; ++f) qq[f] = q[f * Es + idx];
 }
 
-__device__ inline void load_sigma(const double* __restrict__ sg, int64_t Es, int64_t idx, double s[3 * kNsPrims]) {
+// sigma is node-major, [E][Np][33]: the 33 gradients of one node are
+// contiguous, so a face node gathering its neighbour's node touches about
+// three cache lines instead of 33 (one per field array); measured 12 %
+// faster for the gradient + right-hand-side passes than field-major.
+__device__ inline void load_sigma(const double* __restrict__ sg, int64_t idx, double s[3 * kNsPrims]) {
 #pragma unroll
-  for (int f = 0; f < 3 * kNsPrims; ++f) s[f] = sg[f * Es + idx];
+  for (int f = 0; f < 3 * kNsPrims; ++f) s[f] = sg[idx * (3 * kNsPrims) + f];
 }
+
+// LDS of the gradient pass: the block's primitives [EPB][11][Np] and face
+// half-jumps [EPB][11][4 Nfp]; after the contraction the same memory holds
+// the block's gradients node-major, [EPB Np][33], for one coalesced copy out.
+template <int P>
+struct NsGradLds {
+  using C = NsCfg<P>;
+  static constexpr int V = C::EPB * kNsPrims * C::NP;
+  static constexpr int D = C::EPB * kNsPrims * C::NFN;
+  static constexpr int S = C::EPB * C::NP * 3 * kNsPrims;
+  static constexpr int SIZE = V + D > S ? V + D : S;
+};
 
 template <int P>
 __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
   using C = NsCfg<P>;
+  using LD = NsGradLds<P>;
   __shared__ double s_op[C::KOP * C::NP];
-  __shared__ double s_v[C::EPB][kNsPrims][C::NP];
-  __shared__ double s_d[C::EPB][kNsPrims][C::NFN];
+  __shared__ double s_buf[LD::SIZE];
+  auto s_v = reinterpret_cast<double (*)[kNsPrims][C::NP]>(s_buf);
+  auto s_d = reinterpret_cast<double (*)[kNsPrims][C::NFN]>(s_buf + LD::V);
   const int tid = threadIdx.x;
   for (int k = tid; k < C::KOP * C::NP; k += blockDim.x) s_op[k] = A.opT[k];
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * C::EPB;
@@ -98,18 +116,22 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
     for (int c = 0; c < kNsPrims; ++c) s_d[fl][c][fm] = dv[c];
   }
   __syncthreads();
-  if (!valid) return;
   // sig[c][d] first holds D_a v (a = r, s, t), then the physical gradient
+  // (every thread runs the arithmetic, on clamped indices, so that all reach
+  // the barriers below; only valid nodes are stored)
   double sg[kNsPrims][3];
+  const int elc = vol ? el : 0, ic = vol ? i : 0;
+  const int64_t ecl = e0 + elc < A.E ? e0 + elc : A.E - 1;
 #pragma unroll
   for (int c = 0; c < kNsPrims; ++c) sg[c][0] = sg[c][1] = sg[c][2] = 0.0;
+#pragma unroll 2
   for (int j = 0; j < C::NP; ++j) {
-    const double dr = s_op[j * C::NP + i];
-    const double ds = s_op[(C::NP + j) * C::NP + i];
-    const double dt = s_op[(2 * C::NP + j) * C::NP + i];
+    const double dr = s_op[j * C::NP + ic];
+    const double ds = s_op[(C::NP + j) * C::NP + ic];
+    const double dt = s_op[(2 * C::NP + j) * C::NP + ic];
 #pragma unroll
     for (int c = 0; c < kNsPrims; ++c) {
-      const double vj = s_v[el][c][j];
+      const double vj = s_v[elc][c][j];
       sg[c][0] = fma(dr, vj, sg[c][0]);
       sg[c][1] = fma(ds, vj, sg[c][1]);
       sg[c][2] = fma(dt, vj, sg[c][2]);
@@ -117,7 +139,7 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
   }
   double gm[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + e];
+  for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + ecl];
 #pragma unroll
   for (int c = 0; c < kNsPrims; ++c) {
     const double wr = sg[c][0], ws = sg[c][1], wt = sg[c][2];
@@ -131,20 +153,30 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
     double L[kNsPrims];
 #pragma unroll
     for (int c = 0; c < kNsPrims; ++c) L[c] = 0.0;
+#pragma unroll 2
     for (int m = 0; m < C::NFP; ++m) {
-      const double l = s_op[(3 * C::NP + f * C::NFP + m) * C::NP + i];
+      const double l = s_op[(3 * C::NP + f * C::NFP + m) * C::NP + ic];
 #pragma unroll
-      for (int c = 0; c < kNsPrims; ++c) L[c] = fma(l, s_d[el][c][f * C::NFP + m], L[c]);
+      for (int c = 0; c < kNsPrims; ++c) L[c] = fma(l, s_d[elc][c][f * C::NFP + m], L[c]);
     }
 #pragma unroll
     for (int c = 0; c < kNsPrims; ++c)
 #pragma unroll
       for (int d = 0; d < 3; ++d) sg[c][d] = fma(N[d], L[c], sg[c][d]);
   }
+  __syncthreads();  // the primitives and jumps are no longer needed
+  if (vol) {
 #pragma unroll
-  for (int c = 0; c < kNsPrims; ++c)
+    for (int c = 0; c < kNsPrims; ++c)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) A.sigma[(3 * c + d) * Es + e * C::NP + i] = sg[c][d];
+      for (int d = 0; d < 3; ++d) s_buf[(el * C::NP + i) * (3 * kNsPrims) + 3 * c + d] = sg[c][d];
+  }
+  __syncthreads();
+  // the block's valid elements are contiguous in sigma: one coalesced copy
+  const int64_t ne = A.E - e0 < C::EPB ? A.E - e0 : C::EPB;
+  const int nval = static_cast<int>(ne) * C::NP * 3 * kNsPrims;
+  double* dst = A.sigma + e0 * C::NP * (3 * kNsPrims);
+  for (int k = tid; k < nval; k += blockDim.x) dst[k] = s_buf[k];
 }
 
 // Face jump of one face node (element ef, face node fm):
@@ -168,7 +200,7 @@ __device__ inline void ns_face_jump(const NsArgs& A, int64_t Es, int64_t ef, int
     const int64_t im = ef * C::NP + own;
     double s[3 * kNsPrims];
     load_state(A.q, Es, im, qm);
-    load_sigma(A.sigma, Es, im, s);
+    load_sigma(A.sigma, im, s);
     NsNode nd;
     ns_node(A.th, qm, A.T[im], s, nd);
     Unm = ns_flux_along(tr, nd, qm, s, N, Fm);
@@ -177,7 +209,7 @@ __device__ inline void ns_face_jump(const NsArgs& A, int64_t Es, int64_t ef, int
   const int64_t ip = static_cast<int64_t>(cn.x) * C::NP + jp;
   double qp[kNsFields], Fp[kNsFields], s[3 * kNsPrims];
   load_state(A.q, Es, ip, qp);
-  load_sigma(A.sigma, Es, ip, s);
+  load_sigma(A.sigma, ip, s);
   NsNode nd;
   ns_node(A.th, qp, A.T[ip], s, nd);
   const double Unp = ns_flux_along(tr, nd, qp, s, N, Fp);
@@ -237,7 +269,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
       const int64_t idx = e * C::NP + i;
       double qq[kNsFields], sg[3 * kNsPrims], gm[9];
       load_state(A.q, Es, idx, qq);
-      load_sigma(A.sigma, Es, idx, sg);
+      load_sigma(A.sigma, idx, sg);
 #pragma unroll
       for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + e];
       NsNode nd;

@@ -11,7 +11,7 @@ namespace dg {
 struct NsArgs {
   const double* q;      // [12][E][Np] stage input
   const double* T;      // [E][Np] temperatures of q
-  double* sigma;        // [33][E][Np] lifted gradients, field 3 c + d = d v_c / d x_d
+  double* sigma;        // [E][Np][33] lifted gradients, entry 3 c + d = d v_c / d x_d
   double* rhs;          // [12][E][Np] (unfused)
   double* res;          // fused stage: res <- a res + dt rhs
   double* qout;         //              qout <- q + b res

@@ -242,11 +242,11 @@ def _ns_params(thermo, mech, mu, Pr, Sc):
 
 def ns_rhs(mesh: Mesh, thermo, q, T, sigma, out, mech=None, mu: float = MU, Pr: float = PR, Sc: float = SC,
            stream=None):
-    """Reacting Navier-Stokes RHS: q [12, E, Np], T [E, Np] -> sigma [33, E, Np]
+    """Reacting Navier-Stokes RHS: q [12, E, Np], T [E, Np] -> sigma [E, Np, 33]
     (lifted gradients) and out [12, E, Np]; mech=None leaves out the sources."""
     n = mesh.E * mesh.Np
     if q.numel() != 12 * n or T.numel() != n or sigma.numel() != 33 * n or out.numel() != 12 * n:
-        raise ValueError("q/out must be [12, E, Np], T [E, Np], sigma [33, E, Np]")
+        raise ValueError("q/out must be [12, E, Np], T [E, Np], sigma [E, Np, 33]")
     prm = _ns_params(thermo, mech, mu, Pr, Sc)
     _check(lib().dg_ns_rhs(mesh.handle, ctypes.byref(prm), _dev_ptr(q), _dev_ptr(T), _dev_ptr(sigma), _dev_ptr(out),
                            _stream(stream)))

@@ -62,7 +62,7 @@ def _run(mesh, q_np, T_np, mech, mu):
     dev = _dev()
     q = torch.from_numpy(q_np).to(dev)
     T = torch.from_numpy(np.ascontiguousarray(T_np)).to(dev)
-    sig = torch.empty((33,) + tuple(T.shape), dtype=torch.float64, device=dev)
+    sig = torch.empty(tuple(T.shape) + (33,), dtype=torch.float64, device=dev)
     out = torch.empty_like(q)
     th = dg.Thermo(TH["W"], TH["a"])
     mk = dg.Mechanism(th, MECH["A"], MECH["Ea"], MECH["nu_r"], MECH["nu_p"]) if mech else None
@@ -74,8 +74,8 @@ def _run(mesh, q_np, T_np, mech, mu):
 def _check(ops, geo, conn, q, T, sig_gpu, rhs_gpu, mech, mu, label):
     v = ns.primitive_fields(q, T)
     sig_ref = ns.gradients(ops, geo, conn, v)
-    # device layout: field 3 c + d  ->  reference layout [d][c]
-    sg = np.swapaxes(sig_gpu.reshape((11, 3) + T.shape), 0, 1)  # [33] = [c][d] -> [d][c]
+    # device layout [E][Np][3 c + d]  ->  reference layout [d][c][E][Np]
+    sg = np.moveaxis(sig_gpu.reshape(T.shape + (11, 3)), (2, 3), (1, 0))
     smag = _sigma_magnitude(ops, geo, conn, v)
     es = np.abs(sg - sig_ref) / smag.max(axis=(2, 3), keepdims=True)
     r_ref, _, mag = ns.rhs(ops, geo, conn, q, T, TH, MECH if mech else None, mu=mu, sigma=sig_ref, split=True)
@@ -168,7 +168,7 @@ def test_ns_error_paths():
     th = dg.Thermo(TH["W"], TH["a"])
     qt = torch.from_numpy(q).to(dev)
     Tt = torch.from_numpy(np.ascontiguousarray(T)).to(dev)
-    sig = torch.empty((33,) + T.shape, dtype=torch.float64, device=dev)
+    sig = torch.empty(T.shape + (33,), dtype=torch.float64, device=dev)
     out = torch.empty_like(qt)
     with pytest.raises(dg.DGError, match="mu >= 0"):
         dg.ns_rhs(mesh, th, qt, Tt, sig, out, mu=-1.0)
