@@ -362,8 +362,9 @@ def main():
                     help="only run 5 plain device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by element "
-              "partition across GPUs, which this build does not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the method would shard by "
+              "element partition across GPUs with a face-trace exchange per stage; only one GPU is run)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

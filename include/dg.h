@@ -49,7 +49,7 @@ typedef enum {
   DG_ERR_HIP = 4,         /* a HIP runtime call failed (message carries its text) */
   DG_ERR_NOCONV = 5,      /* iterative solve did not converge */
   DG_ERR_NONFINITE = 6,   /* non-finite value detected */
-  DG_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+  DG_ERR_UNSUPPORTED = 7  /* valid request the library does not implement */
 } dg_status;
 
 /* Precision of the element-local contractions (volume divergence and lift)
