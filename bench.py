@@ -71,8 +71,8 @@ def stored_traffic():
 
 def cpu_baseline(xyz, vid, q_np, p, sample_elems):
     """Oracle RHS timed on a contiguous sample of elements (BLAS limited to one
-    thread, so one core does the work).  Returns (record, element ids, oracle
-    RHS on them)."""
+    thread, so one core does the work).  q_np maps node coordinates [E, Np, 3]
+    to the state.  Returns (record, element ids, oracle RHS on them)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import euler as oe, mesh as om, reference_element as ore
@@ -80,6 +80,9 @@ def cpu_baseline(xyz, vid, q_np, p, sample_elems):
     geo = om.geometry(xyz)
     conn = om.connectivity(vid, p)
     idx = np.arange(min(sample_elems, xyz.shape[0]))
+    # the oracle's own nodes: the same smooth state evaluated there (it agrees
+    # with the library's nodes to rounding), so no oracle input comes from the library
+    q_np = q_np(om.node_coordinates(xyz, ops["rst"]))
     with threadpool_limits(limits=1):
         oe.rhs(ops, geo, conn, q_np, elems=idx[:1024])
         t0 = time.perf_counter()
@@ -447,7 +450,8 @@ def main():
             (rec if mode == head else variants[mode])["lsrk_launch"] = cfg
         del work, qs
     if args.cpu_sample > 0:
-        cpu, idx, ref = cpu_baseline(xyz, vid, q_np, p, args.cpu_sample)
+        state = lambda Xn: wl.vortex_state(Xn, pert=wl.density_perturbation(WORKLOAD["pert_seed"]))
+        cpu, idx, ref = cpu_baseline(xyz, vid, state, p, args.cpu_sample)
         rec["cpu_baseline"] = cpu
         idx_t = torch.from_numpy(idx).to(dev)
         for mode in modes:

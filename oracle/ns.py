@@ -107,17 +107,21 @@ def viscous_flux(q, T, sigma, th, mu=MU, Pr=PR, Sc=SC):
     return F
 
 
-def gradients(ops, geo, conn, v):
-    """BR1 pass 1: sigma[d][nv][E][Np] of the nodal fields v[nv][E][Np]."""
+def gradients(ops, geo, conn, v, elems=None):
+    """BR1 pass 1: sigma[d][nv][E][Np] of the nodal fields v[nv][E][Np].
+    With elems (element ids), only at those elements:
+    sigma[d][nv][len(elems)][Np] (the neighbour traces still come from v)."""
+    ix = np.arange(v.shape[1]) if elems is None else np.asarray(elems)
     Nfp = ops["Nfp"]
     fm = ops["Fmask"].reshape(-1)
-    rx = geo["rst_x"]  # [E, a, d]
-    Dv = [v @ D.T for D in (ops["Dr"], ops["Ds"], ops["Dt"])]  # D_a v
-    vM = v[:, :, fm]
-    vP = v[:, conn["mapP_elem"], conn["mapP_node"]]
-    n = np.repeat(geo["normals"], Nfp, axis=1)  # [E, 4Nfp, 3]
-    Fs = np.repeat(geo["Fscale"], Nfp, axis=1)
-    out = np.empty((3,) + v.shape)
+    rx = geo["rst_x"][ix]  # [E, a, d]
+    vE = v[:, ix]
+    Dv = [vE @ D.T for D in (ops["Dr"], ops["Ds"], ops["Dt"])]  # D_a v
+    vM = vE[:, :, fm]
+    vP = v[:, conn["mapP_elem"][ix], conn["mapP_node"][ix]]
+    n = np.repeat(geo["normals"][ix], Nfp, axis=1)  # [E, 4Nfp, 3]
+    Fs = np.repeat(geo["Fscale"][ix], Nfp, axis=1)
+    out = np.empty((3,) + vE.shape)
     for d in range(3):
         vol = sum(rx[None, :, a, d, None] * Dv[a] for a in range(3))
         surf = (Fs * n[..., d] * 0.5 * (vP - vM)) @ ops["LIFT"].T
@@ -125,37 +129,50 @@ def gradients(ops, geo, conn, v):
     return out
 
 
-def rhs(ops, geo, conn, q, T, th, mech=None, mu=MU, Pr=PR, Sc=SC, sigma=None, split=False):
+def rhs(ops, geo, conn, q, T, th, mech=None, mu=MU, Pr=PR, Sc=SC, sigma=None, split=False, elems=None):
     """Reacting NS right-hand side of q[5 + K][E][Np] at temperatures T[E][Np].
     mech=None leaves out the chemical sources.  sigma (optional) are the
-    pass-1 gradients; computed when not given.  split=True also returns
-    (sigma, term magnitude) where the magnitude is
+    pass-1 gradients of the whole mesh; computed when not given.  elems
+    (optional element ids) restricts the result to those elements (the
+    gradients are then computed only where needed: at the elements and at
+    their face neighbours).  split=True also returns (sigma at the result's
+    elements, term magnitude) where the magnitude is
     sum_a |D_a| |G_a| + |LIFT| |Delta| (the dot-product error-bound scale)."""
+    ix = np.arange(q.shape[1]) if elems is None else np.asarray(elems)
     Nfp = ops["Nfp"]
     fm = ops["Fmask"].reshape(-1)
-    if sigma is None:
+    me, mn = conn["mapP_elem"][ix], conn["mapP_node"][ix]
+    if sigma is not None:
+        sE, sP = sigma[:, :, ix], sigma[:, :, me, mn]
+    elif elems is None:
         sigma = gradients(ops, geo, conn, primitive_fields(q, T))
-    Fi, _, _ = inviscid_flux(q, T, th)
-    Fv = viscous_flux(q, T, sigma, th, mu, Pr, Sc)
+        sE, sP = sigma, sigma[:, :, me, mn]
+    else:
+        S = np.unique(np.concatenate([ix, me.ravel()]))
+        sS = gradients(ops, geo, conn, primitive_fields(q, T), elems=S)
+        sE = sS[:, :, np.searchsorted(S, ix)]
+        sP = sS[:, :, np.searchsorted(S, me), mn]
+    qE, TE = q[:, ix], T[ix]
+    Fi, _, _ = inviscid_flux(qE, TE, th)
+    Fv = viscous_flux(qE, TE, sE, th, mu, Pr, Sc)
     F = Fi - Fv
-    rx = geo["rst_x"]
-    out = np.zeros_like(q)
-    mag = np.zeros_like(q)
+    rx = geo["rst_x"][ix]
+    out = np.zeros_like(qE)
+    mag = np.zeros_like(qE)
     for a, D in enumerate((ops["Dr"], ops["Ds"], ops["Dt"])):
         G = sum(rx[None, :, a, d, None] * F[d] for d in range(3))
         out -= G @ D.T
         mag += np.abs(G) @ np.abs(D).T
 
-    me, mn = conn["mapP_elem"], conn["mapP_node"]
-    qM, qP = q[:, :, fm], q[:, me, mn]
-    TM, TP = T[:, fm], T[me, mn]
-    sM, sP = sigma[:, :, :, fm], sigma[:, :, me, mn]
+    qM, qP = qE[:, :, fm], q[:, me, mn]
+    TM, TP = TE[:, fm], T[me, mn]
+    sM = sE[:, :, :, fm]
     FiM, uM, cM = inviscid_flux(qM, TM, th)
     FiP, uP, cP = inviscid_flux(qP, TP, th)
     FvM = viscous_flux(qM, TM, sM, th, mu, Pr, Sc)
     FvP = viscous_flux(qP, TP, sP, th, mu, Pr, Sc)
-    n = np.repeat(geo["normals"], Nfp, axis=1)
-    Fs = np.repeat(geo["Fscale"], Nfp, axis=1)
+    n = np.repeat(geo["normals"][ix], Nfp, axis=1)
+    Fs = np.repeat(geo["Fscale"][ix], Nfp, axis=1)
     nd = [n[..., d] for d in range(3)]
     un_M = sum(uM[d] * nd[d] for d in range(3))
     un_P = sum(uP[d] * nd[d] for d in range(3))
@@ -166,10 +183,10 @@ def rhs(ops, geo, conn, q, T, th, mech=None, mu=MU, Pr=PR, Sc=SC, sigma=None, sp
     out += delta @ ops["LIFT"].T
     mag += np.abs(delta) @ np.abs(ops["LIFT"]).T
     if mech is not None:
-        rho = q[0]
-        out[5:] += th_.sources(rho, T, q[5:] / rho, th, mech)
+        rho = qE[0]
+        out[5:] += th_.sources(rho, TE, qE[5:] / rho, th, mech)
     if split:
-        return out, sigma, mag
+        return out, sE, mag
     return out
 
 

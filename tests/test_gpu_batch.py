@@ -218,3 +218,40 @@ def test_batch_error_paths():
     with pytest.raises(dg.DGError, match="overlaps"):
         b.bind(fake_q, overl, torch.tensor(dts, dtype=torch.float64, device=dev))
     assert b.get_config() == dict(waves_per_block=4, blocks_per_cu=2, order=0, xcd_chunks=0, per_order=1)
+
+
+def test_full_size_batch_equals_separate_steps():
+    """The benchmark's batched workload in full: 64 boxes of 4^3..40^3 cubes
+    (7.93M tets, 131.5M nodes), p = 1..4 mixed, FP32 contractions.  One
+    graph-replayed batched step in each per-order mode equals 64 separate
+    single-mesh steps bitwise (compared on the device)."""
+    dev = _dev()
+    specs = wl.batch_specs()
+    meshes, q0, dts = [], [], []
+    for s in specs:
+        xyz, vid = wl.kuhn_box_mesh(s["n"], 10.0, s["jitter"], s["mesh_seed"])
+        m = dg.Mesh(s["order"], xyz, vid)
+        q0.append(torch.from_numpy(wl.vortex_state(m.nodes(), beta=s["beta"], center=s["center"])).to(dev))
+        meshes.append(m)
+        dts.append(0.2 * (10.0 / s["n"]) / ((s["order"] + 1) ** 2 * 2.0))
+    assert sum(m.E for m in meshes) == 7931190
+    ref = []
+    for m, q, d in zip(meshes, q0, dts):
+        r = q.clone()
+        w = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
+        dg.rk_step(m, r, w, 0.0, d, "fp32")
+        ref.append(r)
+        del w
+    b = dg.Batch(meshes, "fp32")
+    dt = torch.tensor(dts, dtype=torch.float64, device=dev)
+    for per_order in (1, 2):
+        b.set_config(per_order=per_order)
+        qs = [q.clone() for q in q0]
+        works = [torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev) for q in qs]
+        b.bind(qs, works, dt)
+        b.rk_step(use_graph=True)
+        torch.cuda.synchronize()
+        for i, (a, r) in enumerate(zip(qs, ref)):
+            assert torch.equal(a, r), f"per_order={per_order} mesh {i} (n, p) = ({specs[i]['n']}, {specs[i]['order']})"
+        del qs, works
+    b.close()

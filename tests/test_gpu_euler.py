@@ -130,10 +130,10 @@ def test_rhs_full_size_sampled_p3_48cubed():
     dev = _dev()
     xyz, vid = wl.kuhn_box_mesh(48, 10.0, 0.03, 1002)
     mesh = dg.Mesh(3, xyz, vid)
-    Xg = mesh.nodes()
-    q_np = wl.vortex_state(Xg, pert=wl.density_perturbation(2002))
+    ops = ore.operators(3)
+    q_np = wl.vortex_state(om.node_coordinates(xyz, ops["rst"]), pert=wl.density_perturbation(2002))
     got = _gpu_rhs(mesh, q_np)
-    c = dict(ops=ore.operators(3), geo=om.geometry(xyz), conn=om.connectivity(vid, 3), q=q_np)
+    c = dict(ops=ops, geo=om.geometry(xyz), conn=om.connectivity(vid, 3), q=q_np)
     E = xyz.shape[0]
     rng = np.random.default_rng(12)
     idx = np.unique(np.concatenate([np.arange(16), np.arange(E - 16, E), rng.choice(E, 4096, replace=False)]))

@@ -179,3 +179,51 @@ def test_ns_error_paths():
     st = dg.lib().dg_ns_rhs(mesh.handle, ctypes.byref(prm), dg._dev_ptr(qt), dg._dev_ptr(Tt), dg._dev_ptr(sig),
                             dg._dev_ptr(out), dg._stream(None))
     assert st == 1 and b"model must be 1" in dg.lib().dg_last_error()
+
+
+def test_ns_rhs_full_size_sampled_p3_32cubed():
+    """The reacting workload the benchmark times: 32^3 x 6 = 196,608 tets,
+    p = 3, 1 cm box, 3 % jitter, seeded fronts, sources on, in the launch
+    configuration the benchmark uses.  Gradients and right-hand side of a
+    sample of elements (first and last tiles, 1024 random) against the
+    oracle, which evaluates the gradients only at the sample and its face
+    neighbours; same bar as the small meshes."""
+    n, p = 32, 3
+    xyz, vid = wl.kuhn_box_mesh(n, 0.01, 0.03, 1003)
+    ops = ore.operators(p)
+    geo = om.geometry(xyz)
+    conn = om.connectivity(vid, p)
+    X = om.node_coordinates(xyz, ops["rst"])
+    q = wl.reacting_state(X.reshape(-1, 3), seed=3005, L=0.01, n_cells=n).reshape((12,) + X.shape[:2])
+    T, it = ns.temperature(q, TH)
+    assert np.all(it > 0)
+    mesh = dg.Mesh(p, xyz, vid)
+    sig_gpu, rhs_gpu = _run(mesh, q, T, True, ns.MU)
+    E = xyz.shape[0]
+    ix = np.unique(np.concatenate([np.arange(16), np.arange(E - 16, E),
+                                   np.random.default_rng(13).choice(E, 1024, replace=False)]))
+    r_ref, s_ref, mag = ns.rhs(ops, geo, conn, q, T, TH, MECH, split=True, elems=ix)
+    # gradients: scale of each entry's rounding (as _sigma_magnitude, at the sample)
+    v = ns.primitive_fields(q, T)
+    Nfp = ops["Nfp"]
+    fm = ops["Fmask"].reshape(-1)
+    av = np.abs(v[:, ix])
+    Dv = [av @ np.abs(D).T for D in (ops["Dr"], ops["Ds"], ops["Dt"])]
+    jump = 0.5 * np.abs(v[:, conn["mapP_elem"][ix], conn["mapP_node"][ix]] - v[:, ix][:, :, fm])
+    nn = np.repeat(geo["normals"][ix], Nfp, axis=1)
+    Fs = np.repeat(geo["Fscale"][ix], Nfp, axis=1)
+    smag = np.empty((3,) + av.shape)
+    for d in range(3):
+        smag[d] = sum(np.abs(geo["rst_x"][ix][None, :, a, d, None]) * Dv[a] for a in range(3))
+        smag[d] += (Fs * np.abs(nn[..., d]) * jump) @ np.abs(ops["LIFT"]).T
+    sg = np.moveaxis(sig_gpu[ix].reshape((len(ix), ops["Np"], 11, 3)), (2, 3), (1, 0))
+    es = np.abs(sg - s_ref) / smag.max(axis=(2, 3), keepdims=True)
+    scale = mag.max(axis=(1, 2))
+    w = ot.sources(q[0][ix], T[ix], q[5:, ix] / q[0][ix], TH, MECH)
+    scale[5:] += np.abs(w).max(axis=(1, 2))
+    er = np.abs(rhs_gpu[:, ix] - r_ref).max(axis=(1, 2)) / scale
+    print(f"32^3 sampled ({len(ix)} elements): max sigma err / scale {es.max():.2e}, "
+          f"rhs err / scale {np.array2string(er, precision=1)}")
+    assert np.all(np.isfinite(rhs_gpu)) and np.all(np.isfinite(sig_gpu))
+    assert es.max() <= 1e-12
+    assert np.all(er <= 1e-12)

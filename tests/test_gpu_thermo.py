@@ -103,3 +103,40 @@ def test_thermo_error_paths():
     bad[0, 0] = -1
     with pytest.raises(dg.DGError):
         dg.Mechanism(th, MECH["A"], MECH["Ea"], bad, MECH["nu_p"].astype(np.int32))
+
+
+def test_temperature_and_sources_full_size_sampled():
+    """The learned-guess evaluation size: the 48^3 x 6 p = 3 mesh's 13.27M
+    nodes (1 cm box) with reacting fields, one launch each; the oracle solves
+    and evaluates a random sample of 20,000 nodes (first and last included)
+    to the same bars.  The sources take a seeded temperature field in
+    [300, 2200] K as input on both sides."""
+    dev = _dev()
+    th, mk = _handles()
+    xyz, _ = wl.kuhn_box_mesh(48, 0.01, 0.03, 1002)
+    X = om.node_coordinates(xyz, ore.nodes(3))
+    q_np = wl.reacting_state(X.reshape(-1, 3), seed=3005, L=0.01, n_cells=48)
+    n = q_np.shape[1]
+    T_in = np.random.default_rng(15).uniform(300.0, 2200.0, n)
+    q = torch.from_numpy(q_np).to(dev)
+    T = torch.empty(n, dtype=torch.float64, device=dev)
+    it = torch.empty(n, dtype=torch.int32, device=dev)
+    om_ = torch.empty((7, n), dtype=torch.float64, device=dev)
+    dg.temperature(th, q, T, it, T_default=1000.0)
+    dg.sources(mk, q, torch.from_numpy(T_in).to(dev), om_)
+    torch.cuda.synchronize()
+    idx = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(14).choice(n, 20000, replace=False)]))
+    Tg, itg, wg = T.cpu().numpy()[idx], it.cpu().numpy()[idx], om_.cpu().numpy()[:, idx]
+    qs = np.ascontiguousarray(q_np[:, idx])
+    rho, u, v, w, e, Y = ot.primitives(qs)
+    T_ref, it_ref = ot.newton_temperature(e, Y, TH, 1000.0, tol=1e-10, max_iter=50)
+    print(f"{n} nodes, sample {len(idx)}: max |T - T_oracle| = {np.abs(Tg - T_ref).max():.2e}")
+    assert np.all(itg > 0) and np.abs(Tg - T_ref).max() <= 1e-9
+    assert np.abs(itg - it_ref).max() <= 1
+    w_ref = ot.sources(rho, T_in[idx], Y, TH, MECH)
+    scale = np.abs(w_ref).max(axis=1)
+    inert = scale == 0.0
+    assert np.all(wg[inert] == 0.0)
+    err = np.abs(wg[~inert] - w_ref[~inert]).max(axis=1) / scale[~inert]
+    print("sources err / per-species max (reacting species)", err)
+    assert np.all(err <= 1e-12)

@@ -341,3 +341,29 @@ def test_sources_added_only_to_species():
     w = ot.sources(q[0], T, q[5:] / q[0], TH, MECH)
     assert np.array_equal(r0[:5], r1[:5])
     assert np.allclose(r1[5:] - r0[5:], w, rtol=1e-12, atol=1e-12 * np.abs(w).max())
+
+
+def test_element_subset_matches_the_whole_mesh():
+    """rhs and gradients restricted to a set of elements equal the whole-mesh
+    results at those elements (the subset path computes the gradients only at
+    the elements and their face neighbours)."""
+    p = 2
+    xyz, ops, geo, conn, X = _setup(p, (3, 4, 3), (0.01, 0.01, 0.01), seed=9)
+    q = wl.reacting_state(X.reshape(-1, 3), seed=3006, L=0.01, n_cells=4).reshape((12,) + X.shape[:2])
+    q = q * (1.0 + 1e-3 * np.random.default_rng(5).standard_normal(q.shape))
+    T, it = ns.temperature(q, TH)
+    assert np.all(it > 0)
+    E = q.shape[1]
+    elems = np.random.default_rng(6).choice(E, 17, replace=False)
+    v = ns.primitive_fields(q, T)
+    g_all = ns.gradients(ops, geo, conn, v)
+    g_sub = ns.gradients(ops, geo, conn, v, elems=elems)
+    np.testing.assert_allclose(g_sub, g_all[:, :, elems], rtol=0, atol=1e-14 * np.abs(g_all).max())
+    r_all, s_all, m_all = ns.rhs(ops, geo, conn, q, T, TH, MECH, split=True)
+    r_sub, s_sub, m_sub = ns.rhs(ops, geo, conn, q, T, TH, MECH, split=True, elems=elems)
+    scale = m_all.max(axis=(1, 2))[:, None, None]
+    assert np.all(np.abs(r_sub - r_all[:, elems]) <= 1e-13 * scale)
+    np.testing.assert_allclose(s_sub, s_all[:, :, elems], rtol=0, atol=1e-14 * np.abs(s_all).max())
+    # a given whole-mesh sigma gives the same subset result
+    r_giv = ns.rhs(ops, geo, conn, q, T, TH, MECH, sigma=s_all, elems=elems)
+    assert np.all(np.abs(r_giv - r_all[:, elems]) <= 1e-13 * scale)
