@@ -42,3 +42,27 @@ def test_reference_operators_rejects_bad_order():
     with pytest.raises(dg.DGError) as ei:
         dg.reference_operators(5)
     assert ei.value.status == 1
+
+
+def test_host_side_argument_checks_need_no_device():
+    """Entry points reject null handles and bad arguments before touching a
+    device, with a status code and a message (no exception crosses the ABI)."""
+    import ctypes
+    L = dg.lib()
+    cfg = dg.LaunchConfig(4, 1)
+    assert L.dg_mesh_set_launch(None, 0, ctypes.byref(cfg)) == 1
+    assert b"null" in L.dg_last_error()
+    assert L.dg_mesh_get_launch(None, 0, ctypes.byref(cfg)) == 1
+    prm = dg._params(1.4)
+    assert L.dg_autotune(None, ctypes.byref(prm), 0, None, 3, None, None, None) == 1
+    assert L.dg_rhs(None, ctypes.byref(prm), 0, None, None, None) == 1
+    assert L.dg_rk_step(None, ctypes.byref(prm), 0, None, None, 0.0, 1e-3, None) == 1
+    out = ctypes.c_void_p()
+    assert L.dg_batch_create(None, 0, 1, ctypes.byref(out)) == 1 and not out.value
+    assert L.dg_batch_rk_step(None, ctypes.byref(prm), 1, None) == 1
+    bc = dg.BatchConfig(4, 2, 0, 0, 1)
+    assert L.dg_batch_set_config(None, ctypes.byref(bc)) == 1
+    assert L.dg_lsrk_update(-1, 0.0, 1.0, 1e-3, None, None, None, None) == 1
+    assert L.dg_lsrk_update(0, 0.0, 1.0, 1e-3, None, None, None, None) == 0  # nothing to do
+    # destroying null handles is a no-op
+    assert L.dg_batch_destroy(None) == 0
