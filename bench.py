@@ -204,6 +204,22 @@ def batched_leg(dg, wl, dev, stream, steps):
         stream.synchronize()
         ms_sep = e0.elapsed_time(e1) / steps
     info = batch.info()
+    batch_cfg = cfg
+    # the same workload with split-BF16 contractions, for comparison
+    sb = dg.Batch(meshes, "split_bf16")
+    sb.bind(qs, works, dt)
+    with torch.cuda.stream(stream):
+        cfg_s, _ = sb.autotune(trials=2, stream=stream)
+        sb.rk_step(use_graph=True, stream=stream)
+        stream.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            sb.rk_step(use_graph=True, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms_split = e0.elapsed_time(e1) / steps
+    sb.close()
+    cfg = batch_cfg
     dof_fields = sum(m.E * m.Np for m in meshes) * NF
     finite = all(bool(torch.isfinite(q).all()) for q in qs)
     out = {"workload": "batch64_vortex_n4to40_p1to4", "meshes": len(meshes), "elements": info["n_elem"],
@@ -216,7 +232,10 @@ def batched_leg(dg, wl, dev, stream, steps):
            "launches_per_stage": (info["graph_kernel_nodes"] - 1) // 5 if cfg["per_order"] != 1
            else info["graph_kernel_nodes"] // 6,
            "graph_kernel_nodes_per_step": info["graph_kernel_nodes"], "autotuned": cfg, "mode_ms_per_step": mode_ms,
-           "autotune_best_ms": round(tune_ms, 4), "steps": steps, "state_finite": finite,
+           "autotune_best_ms": round(tune_ms, 4),
+           "split_bf16": {"ms_per_step": round(ms_split, 4),
+                          "value": round(5 * dof_fields / (ms_split * 1e-3) / 1e9, 3), "autotuned": cfg_s},
+           "steps": steps, "state_finite": finite,
            "host_setup_s": round(setup_s, 1)}
     batch.close()
     return out
