@@ -59,7 +59,8 @@ OpLayout op_layout(int p);
 
 // Layout of the reduced-precision operator tables.
 //  FP32:  op32[KS32][NR][64], lane l holding Op[16 rb + l % 16][4 ks + l / 16]
-//         (same K order as the FP64 table), 16-row blocks, rows >= Np zero.
+//         (same K order as the FP64 table), 16-row blocks, rows >= Np zero;
+//         with REM4 the last block holds 4 rows, lane l Op[16 rb + l % 4][4 ks + l / 16].
 //  BF16:  opbf[VKS + FKS][NR][2 (hi, lo)][64][8]: lane l = i + 16 g holds
 //         8 consecutive K slots t = 8 k .. 8 k + 7 of lane group g, where the
 //         volume slots t = 3 s + a map to column a NPP + 4 s + g and the
@@ -67,6 +68,7 @@ OpLayout op_layout(int p);
 //         x = fp32(Op), hi = bf16(x), lo = bf16(x - hi), round to nearest even.
 struct LowpLayout {
   int Np, Nfp, NPP, KV, KL, NR, KS32, VKS, FKS;
+  bool REM4;  // FP32: last of at most two row blocks has at most 4 rows (4x4 blocks)
 };
 LowpLayout lowp_layout(int p);
 

@@ -11,7 +11,13 @@
 //  FP32        v_mfma_f32_16x16x4f32, K stepped by 4, lane (n, g) supplying
 //              k = 4 ks + g (the same node / face-node mapping as FP64);
 //              rows in 16-row blocks, output row 16 rb + 4 g + v in lane (n, g)
-//              register v.
+//              register v.  When the last block holds at most 4 rows (p = 1
+//              and 3) it runs on v_mfma_f32_4x4x1_16b instead: block
+//              (g, n / 4) multiplies the 4 rows by the k = 4 ks + g entries of
+//              elements 4 (n / 4) .. + 3, so lane (n, g) accumulates the
+//              k = g (mod 4) part of each row of element n, and the four lane
+//              groups are summed once after the last k-step (a quarter of the
+//              matrix-core cycles of a padded 16-row block).
 //  split BF16  v_mfma_f32_16x16x32_bf16 with x = hi + lo (hi = bf16(x),
 //              lo = bf16(x - hi)) and Op X ~ Op_hi X_hi + Op_hi X_lo +
 //              Op_lo X_hi accumulated in FP32; the split is taken in FP32
@@ -46,6 +52,9 @@ struct LCfg {
   static constexpr int KV = NPP / 4;        // node steps per lane
   static constexpr int KL = NFP;            // face-node steps per lane
   static constexpr int NR = (NP + 15) / 16; // 16-row blocks
+  // FP32: the last block has at most 4 rows and runs as 4x4 blocks (p = 1
+  // and 3; at p = 4 the extra accumulators would spill)
+  static constexpr bool REM4 = NP % 16 != 0 && NP % 16 <= 4 && NR <= 2;
   static constexpr int KS32 = 3 * KV + KL;  // FP32 k-steps (4 wide)
   static constexpr int VKS = (3 * KV + 7) / 8;  // BF16 volume k-steps (32 wide)
   static constexpr int FKS = (KL + 7) / 8;      // BF16 face k-steps
@@ -68,6 +77,21 @@ struct LowArgs {
   int ntiles;
   double gamma, a, b, dt;
 };
+
+// Lane (n, g) holds in register i the k = g (mod 4) part of row i of a 4-row
+// block for element n; returns the whole of row g.  Reduce-scatter over the
+// four lane groups: rows are halved between lane groups g and g ^ 2, then
+// between g and g ^ 1.  Called by the whole wave.
+__device__ inline float sum_lane_groups(v4f x, int g) {
+  const bool hi = (g & 2) != 0;
+  float k0 = hi ? x[2] : x[0], k1 = hi ? x[3] : x[1];
+  const float s0 = hi ? x[0] : x[2], s1 = hi ? x[1] : x[3];
+  k0 += __shfl_xor(s0, 32);
+  k1 += __shfl_xor(s1, 32);
+  const bool lo = (g & 1) != 0;
+  const float k = lo ? k1 : k0, s = lo ? k0 : k1;
+  return k + __shfl_xor(s, 16);
+}
 
 // Splits 8 staged FP32 slots per field into hi = bf16(x) and lo = bf16(x - hi)
 // (round to nearest even; x - hi is exact in FP32), runs the three products
@@ -151,6 +175,20 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
 
     if constexpr (MODE == 1) {
       const float* op = reinterpret_cast<const float*>(s_op);
+      // 16-row blocks 0 .. NR16 - 1 in acc, the 4-row remainder (REM4) in acc4
+      constexpr int NR16 = C::REM4 ? C::NR - 1 : C::NR;
+      v4f acc4[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) acc4[f] = v4f{0.f, 0.f, 0.f, 0.f};
+      auto mma = [&](const float a, int rb, const double (&B)[5]) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          if (rb < NR16)
+            acc[f][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, static_cast<float>(B[f]), acc[f][rb], 0, 0, 0);
+          else
+            acc4[f] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, static_cast<float>(B[f]), acc4[f], 0, 0, 0);
+        }
+      };
 #pragma unroll
       for (int s = 0; s < C::KV; ++s) {
         const int j = 4 * s + g;
@@ -173,14 +211,11 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int rb = 0; rb < C::NR; ++rb) {
-            const float a = op[((r * C::KV + s) * C::NR + rb) * 64 + lane];
-#pragma unroll
-            for (int f = 0; f < 5; ++f)
-              acc[f][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, static_cast<float>(G[r][f]), acc[f][rb], 0, 0, 0);
-          }
+          for (int rb = 0; rb < C::NR; ++rb) mma(op[((r * C::KV + s) * C::NR + rb) * 64 + lane], rb, G[r]);
       }
-#pragma unroll 2
+      // whole face loop unrolled up to p = 3; at p = 4 by two (registers)
+      constexpr int FU = P < 4 ? C::KL : 2;
+#pragma unroll FU
       for (int s = 0; s < C::KL; ++s) {
         const int fm = 4 * s + g;
         const int face = fm / C::NFP;
@@ -204,12 +239,12 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
         scaled_normal(face, gm, Nx, Ny, Nz);
         lf_jump(qm, qp, Nx, Ny, Nz, A.gamma, D);
 #pragma unroll
-        for (int rb = 0; rb < C::NR; ++rb) {
-          const float a = op[((3 * C::KV + s) * C::NR + rb) * 64 + lane];
+        for (int rb = 0; rb < C::NR; ++rb) mma(op[((3 * C::KV + s) * C::NR + rb) * 64 + lane], rb, D);
+      }
+      // remainder rows: lane (n, g) keeps row 16 NR16 + g of element n in register 0
+      if constexpr (C::REM4) {
 #pragma unroll
-          for (int f = 0; f < 5; ++f)
-            acc[f][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, static_cast<float>(D[f]), acc[f][rb], 0, 0, 0);
-        }
+        for (int f = 0; f < 5; ++f) acc[f][NR16] = v4f{sum_lane_groups(acc4[f], g), 0.f, 0.f, 0.f};
       }
     } else {
       const v8bf* op = reinterpret_cast<const v8bf*>(s_op);  // [k][rb][part][64]
@@ -276,7 +311,12 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
       }
     }
 
-    // store: lane (n, g) register v holds row 16 rb + 4 g + v
+    // store: lane (n, g) register v holds row 16 rb + 4 g + v (in FP32 mode
+    // the REM4 block holds row 16 rb + g in register 0 only)
+    auto out_row = [&](int rb, int v) -> int {
+      if (MODE == 1 && C::REM4 && rb == C::NR - 1) return v == 0 ? 16 * rb + g : C::NP;
+      return 16 * rb + 4 * g + v;
+    };
     if constexpr (STAGED) {
       // through the LDS tile buffer (the state is no longer needed there):
       // coalesced stores, and in the fused stage all res / q loads of a
@@ -289,7 +329,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
           for (int rb = 0; rb < C::NR; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int row = 16 * rb + 4 * g + v;
+              const int row = out_row(rb, v);
               if (row < C::NP) sq[f * TQ + n * C::NP + row] = static_cast<double>(acc[f][rb][v]);
             }
       }
@@ -303,7 +343,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
           for (int rb = 0; rb < C::NR; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int row = 16 * rb + 4 * g + v;
+              const int row = out_row(rb, v);
               if (row < C::NP) A.rhs[f * Es + e * C::NP + row] = static_cast<double>(acc[f][rb][v]);
             }
       }
@@ -316,7 +356,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
         for (int rb = 0; rb < C::NR; ++rb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int row = 16 * rb + 4 * g + v;
+            const int row = out_row(rb, v);
             const int64_t idx = f * Es + e * C::NP + (row < C::NP ? row : C::NP - 1);  // clamped: unconditional
             rv[rb][v] = A.a != 0.0 ? A.res[idx] : 0.0;
             qv[rb][v] = q[idx];
@@ -325,7 +365,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
         for (int rb = 0; rb < C::NR; ++rb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int row = 16 * rb + 4 * g + v;
+            const int row = out_row(rb, v);
             if (row < C::NP)
               stage_store(f * Es + e * C::NP + row, static_cast<double>(acc[f][rb][v]), rv[rb][v], qv[rb][v], A.res,
                           A.qout, A.a, A.b, A.dt);

@@ -108,9 +108,11 @@ void build_lowp_tables(const RefElem& R, std::vector<float>& op32, std::vector<u
   op32.assign(static_cast<size_t>(L.KS32) * L.NR * 64, 0.f);
   for (int ks = 0; ks < L.KS32; ++ks)
     for (int rb = 0; rb < L.NR; ++rb)
-      for (int l = 0; l < 64; ++l)
+      for (int l = 0; l < 64; ++l) {
+        const int row = L.REM4 && rb == L.NR - 1 ? 16 * rb + l % 4 : 16 * rb + l % 16;
         op32[(static_cast<size_t>(ks) * L.NR + rb) * 64 + l] =
-            static_cast<float>(op_entry(R, L.NPP, 16 * rb + l % 16, 4 * ks + l / 16));
+            static_cast<float>(op_entry(R, L.NPP, row, 4 * ks + l / 16));
+      }
   opbf.assign(static_cast<size_t>(L.VKS + L.FKS) * L.NR * 2 * 64 * 8, 0);
   for (int k = 0; k < L.VKS + L.FKS; ++k)
     for (int rb = 0; rb < L.NR; ++rb)

@@ -73,6 +73,7 @@ LowpLayout lowp_layout(int p) {
   L.KV = L.NPP / 4;
   L.KL = L.Nfp;
   L.NR = (L.Np + 15) / 16;
+  L.REM4 = L.Np % 16 != 0 && L.Np % 16 <= 4 && L.NR <= 2;
   L.KS32 = 3 * L.KV + L.KL;
   L.VKS = (3 * L.KV + 7) / 8;
   L.FKS = (L.KL + 7) / 8;
