@@ -132,8 +132,9 @@ dg_status dg_rk_step(dg_mesh m, const dg_params* prm, dg_precision prec, double*
 /* Launch configuration of one mesh's RHS and Runge-Kutta kernels for one
  * contraction precision.  Results do not depend on it (bitwise). */
 typedef struct {
-  int waves_per_block; /* 16-element tiles per block: 2 or 4 (p = 4: 2 only; a
-                          request of 4 runs 2) */
+  int waves_per_block; /* 16-element tiles per block: 2 or 4 up to p = 3.  At
+                          p = 4 the FP64 kernel runs 2 and the FP32 / split
+                          BF16 kernels 1, whatever is requested. */
   int rk_fused;        /* 1 = fused stage launches, 0 = RHS launch + update */
 } dg_launch_config;
 /* Initial configuration of every precision: {4, 1}.  Set and get are

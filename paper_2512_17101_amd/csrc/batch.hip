@@ -92,9 +92,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2))) v
 
 // Per-order kernel: the items [p_begin[P], p_end[P]) all have order P; one
 // wave per item, its tile's state staged in LDS, the register budget of this
-// order alone (the single-mesh kernel's launch shape).
+// order alone (the single-mesh kernel's launch shape: one-tile blocks and
+// face tables read from memory at p = 4).
 template <int P>
-constexpr int order_waves() { return P >= 4 ? 2 : 4; }
+constexpr int order_waves() { return P >= 4 ? 1 : 4; }
 
 template <int P, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P < 4 ? 3 : 2))) void batch_order_kernel(
@@ -102,11 +103,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P < 4 ? 3 :
   using C = LCfg<P>;
   constexpr int W = order_waves<P>();
   __shared__ double s_q[W][5 * 16 * C::NP];
-  __shared__ uint8_t s_nb[4 * 24 * C::NFP];
-  __shared__ int s_fm[4 * C::NFP];
-  for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nb[i] = L.tabs.nb[P][i];
-  for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fm[i] = L.tabs.fm[P][i];
-  __syncthreads();
+  __shared__ uint8_t s_nbl[lowp_lds_tables<P>() ? 4 * 24 * C::NFP : 4];
+  __shared__ int s_fml[lowp_lds_tables<P>() ? 4 * C::NFP : 1];
+  if constexpr (lowp_lds_tables<P>()) {
+    for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nbl[i] = L.tabs.nb[P][i];
+    for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fml[i] = L.tabs.fm[P][i];
+    __syncthreads();
+  }
+  const uint8_t* s_nb = lowp_lds_tables<P>() ? s_nbl : L.tabs.nb[P];
+  const int* s_fm = lowp_lds_tables<P>() ? s_fml : L.tabs.fm[P];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
   const int64_t i = L.p_begin[P] + static_cast<int64_t>(blockIdx.x) * W + wave;
   if (i >= L.p_end[P]) return;

@@ -62,6 +62,12 @@ struct LCfg {
   static constexpr int OPBF = (VKS + FKS) * NR * 2 * 64 * 8;  // bf16 values (hi, lo)
 };
 
+// Whether a kernel of order P keeps the face tables in LDS: up to p = 3; at
+// p = 4 the 22.4 KB state tile alone bounds the waves per CU, so one-tile
+// blocks read the (cache-resident) tables from memory instead.
+template <int P>
+constexpr bool lowp_lds_tables() { return P < 4; }
+
 struct LowArgs {
   const double* __restrict__ q;
   double* __restrict__ rhs;

@@ -10,9 +10,12 @@ namespace {
 using namespace lowp;
 
 // W waves per block (one 16-element tile each; the tile's state is staged in
-// LDS, 5 x 16 Np doubles per wave: two or four up to p = 3, two at p = 4, as
-// the mesh's launch configuration says) and the register target: three
-// waves per SIMD up to p = 3, two at p = 4.
+// LDS, 5 x 16 Np doubles per wave: two or four up to p = 3, as the mesh's
+// launch configuration says) and the register target: three waves per SIMD
+// up to p = 3, two at p = 4.  At p = 4 the state tile alone is 22.4 KB, so
+// LDS bounds the waves per CU: one-tile blocks with the face tables read from
+// memory (cache-resident) fit seven per CU against six for two-tile blocks
+// with LDS tables (measured 9-10 % faster).
 template <int P, int MODE>
 constexpr int lowp_wpe() { return P < 4 ? 3 : 2; }
 
@@ -21,11 +24,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lowp_wpe
     LowArgs A) {
   using C = LCfg<P>;
   __shared__ double s_q[W][5 * 16 * C::NP];
-  __shared__ uint8_t s_nb[4 * 24 * C::NFP];
-  __shared__ int s_fm[4 * C::NFP];
-  for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nb[i] = A.nbtab[i];
-  for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fm[i] = A.fmask[i];
-  __syncthreads();
+  __shared__ uint8_t s_nbl[lowp_lds_tables<P>() ? 4 * 24 * C::NFP : 4];
+  __shared__ int s_fml[lowp_lds_tables<P>() ? 4 * C::NFP : 1];
+  if constexpr (lowp_lds_tables<P>()) {
+    for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nbl[i] = A.nbtab[i];
+    for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fml[i] = A.fmask[i];
+    __syncthreads();
+  }
+  const uint8_t* s_nb = lowp_lds_tables<P>() ? s_nbl : A.nbtab;
+  const int* s_fm = lowp_lds_tables<P>() ? s_fml : A.fmask;
   // the operator table is read from memory (cache-resident): LDS holds the states
   const uint32_t* op = MODE == 1 ? reinterpret_cast<const uint32_t*>(A.op32) : reinterpret_cast<const uint32_t*>(A.opbf);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
@@ -44,8 +51,10 @@ void launch_lowp_pw(const Mesh& m, const LowArgs& args, bool fused, hipStream_t 
 
 template <int P, int MODE>
 dg_status launch_lowp_p(const Mesh& m, const LowArgs& args, bool fused, hipStream_t s) {
-  if (P < 4 && m.launch[MODE].waves_per_block == 4)
-    launch_lowp_pw<P, MODE, P < 4 ? 4 : 2>(m, args, fused, s);
+  if constexpr (P >= 4)
+    launch_lowp_pw<P, MODE, 1>(m, args, fused, s);
+  else if (m.launch[MODE].waves_per_block == 4)
+    launch_lowp_pw<P, MODE, 4>(m, args, fused, s);
   else
     launch_lowp_pw<P, MODE, 2>(m, args, fused, s);
   DG_HIP(hipGetLastError());
