@@ -37,7 +37,8 @@ NF = 5
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "rhs_euler_fp64_p3_48cubed_pmc.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2512_17101_amd", "csrc", "rhs_euler.hip")
+# device sources of the FP64 RHS kernel (the kernel file, then its tile helpers)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2512_17101_amd", "csrc", f) for f in ("rhs_euler.hip", "euler_point.hpp")]
 
 
 def algorithmic_counts(p: int):
@@ -53,6 +54,13 @@ def algorithmic_counts(p: int):
     return flops, bytes_
 
 
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def stored_traffic():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
@@ -63,7 +71,7 @@ def stored_traffic():
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    sha = kernel_source_sha()
     if kv.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in kv:
         return None
     return float(kv["traffic_bytes_per_launch"])
