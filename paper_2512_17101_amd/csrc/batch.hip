@@ -103,11 +103,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P < 4 ? 3 :
   using C = LCfg<P>;
   constexpr int W = order_waves<P>();
   __shared__ double s_q[W][5 * 16 * C::NP];
-  __shared__ uint8_t s_nbl[lowp_lds_tables<P>() ? 4 * 24 * C::NFP : 4];
+  __shared__ __align__(4) uint8_t s_nbl[lowp_lds_tables<P>() ? 4 * 24 * C::NFP : 4];
   __shared__ int s_fml[lowp_lds_tables<P>() ? 4 * C::NFP : 1];
   if constexpr (lowp_lds_tables<P>()) {
-    for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nbl[i] = L.tabs.nb[P][i];
-    for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fml[i] = L.tabs.fm[P][i];
+    stage_face_tables<C::NFP, 64 * W>(s_nbl, s_fml, L.tabs.nb[P], L.tabs.fm[P], threadIdx.x);
     __syncthreads();
   }
   const uint8_t* s_nb = lowp_lds_tables<P>() ? s_nbl : L.tabs.nb[P];

@@ -83,6 +83,34 @@ __device__ inline void lf_jump(const double qm[5], const double qp[5], double Nx
   D[4] = 0.5 * ((qm[4] + pm) * Unm - (qp[4] + pp) * Unp) - 0.5 * lamFs * (qm[4] - qp[4]);
 }
 
+// Copies the face tables of order P's element (neighbour volume node of each
+// face node per face and neighbour code, nbtab [4][24][Nfp] bytes; face-node
+// mask fmask [4 Nfp]) into LDS, thread t of NT: every load is issued before
+// the first write, so a block starts after one memory latency instead of one
+// per loop trip.  Indices are clamped, the writes guarded; the caller
+// synchronises the block afterwards.
+template <int NFP, int NT>
+__device__ inline void stage_face_tables(uint8_t* s_nb, int* s_fm, const uint8_t* __restrict__ nbtab,
+                                         const int* __restrict__ fmask, int t) {
+  constexpr int NBW = 4 * 24 * NFP / 4;  // 32-bit words (96 Nfp bytes)
+  constexpr int KW = (NBW + NT - 1) / NT;
+  const uint32_t* nb32 = reinterpret_cast<const uint32_t*>(nbtab);
+  uint32_t w[KW];
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int i = t + k * NT;
+    w[k] = nb32[i < NBW ? i : NBW - 1];
+  }
+  const int fmv = fmask[t < 4 * NFP ? t : 4 * NFP - 1];
+  uint32_t* s_nb32 = reinterpret_cast<uint32_t*>(s_nb);
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int i = t + k * NT;
+    if (i < NBW) s_nb32[i] = w[k];
+  }
+  if (t < 4 * NFP) s_fm[t] = fmv;
+}
+
 // Values per lane in one round of a tile's loads (at most 25 doubles per
 // lane in flight: one round up to p = 3, three at p = 4).
 template <int TQ>

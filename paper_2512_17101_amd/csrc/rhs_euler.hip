@@ -78,10 +78,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ?
   constexpr int NB16 = C::NB16 > 0 ? C::NB16 : 1;
   constexpr int NB4 = C::NB4 > 0 ? C::NB4 : 1;
   __shared__ double s_q[TL::WAVES][5 * TL::TQ];
-  __shared__ uint8_t s_nb[4 * 24 * C::NFP];
+  __shared__ __align__(4) uint8_t s_nb[4 * 24 * C::NFP];
   __shared__ int s_fm[4 * C::NFP];
-  for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nb[i] = A.nbtab[i];
-  for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fm[i] = A.fmask[i];
+  stage_face_tables<C::NFP, 64 * W>(s_nb, s_fm, A.nbtab, A.fmask, threadIdx.x);
   __syncthreads();
   const double* __restrict__ op = A.op;
 

@@ -24,11 +24,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lowp_wpe
     LowArgs A) {
   using C = LCfg<P>;
   __shared__ double s_q[W][5 * 16 * C::NP];
-  __shared__ uint8_t s_nbl[lowp_lds_tables<P>() ? 4 * 24 * C::NFP : 4];
+  __shared__ __align__(4) uint8_t s_nbl[lowp_lds_tables<P>() ? 4 * 24 * C::NFP : 4];
   __shared__ int s_fml[lowp_lds_tables<P>() ? 4 * C::NFP : 1];
   if constexpr (lowp_lds_tables<P>()) {
-    for (int i = threadIdx.x; i < 4 * 24 * C::NFP; i += blockDim.x) s_nbl[i] = A.nbtab[i];
-    for (int i = threadIdx.x; i < 4 * C::NFP; i += blockDim.x) s_fml[i] = A.fmask[i];
+    stage_face_tables<C::NFP, 64 * W>(s_nbl, s_fml, A.nbtab, A.fmask, threadIdx.x);
     __syncthreads();
   }
   const uint8_t* s_nb = lowp_lds_tables<P>() ? s_nbl : A.nbtab;
