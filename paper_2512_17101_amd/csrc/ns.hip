@@ -28,6 +28,24 @@
 namespace dg {
 namespace {
 
+// Copies N doubles into LDS, thread t of NT: every load is issued before
+// the first write (one memory latency instead of one per loop trip).
+template <int N, int NT>
+__device__ inline void stage_block_array(double* dst, const double* __restrict__ src, int t) {
+  constexpr int K = (N + NT - 1) / NT;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t + k * NT;
+    v[k] = src[i < N ? i : N - 1];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t + k * NT;
+    if (i < N) dst[i] = v[k];
+  }
+}
+
 template <int P>
 struct NsCfg {
   static constexpr int NP = (P + 1) * (P + 2) * (P + 3) / 6;
@@ -72,19 +90,56 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
   auto s_v = reinterpret_cast<double (*)[kNsPrims][C::NP]>(s_buf);
   auto s_d = reinterpret_cast<double (*)[kNsPrims][C::NFN]>(s_buf + LD::V);
   const int tid = threadIdx.x;
-  for (int k = tid; k < C::KOP * C::NP; k += blockDim.x) s_op[k] = A.opT[k];
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * C::EPB;
   const int64_t Es = A.E * C::NP;
   const int el = tid / C::NP, i = tid - el * C::NP;
   const bool vol = tid < C::EPB * C::NP;
   const int64_t e = e0 + el;
   const bool valid = vol && e < A.E;
+  const int elc = vol ? el : 0, ic = vol ? i : 0;
+  const int64_t ecl = e0 + elc < A.E ? e0 + elc : A.E - 1;
+  // Every memory read of the first phase is requested before any is used:
+  // the operator (for LDS), the metric, this thread's volume node and the
+  // neighbour nodes of its face nodes (indices clamped; results of
+  // out-of-range slots are discarded below).
+  constexpr int NOP = C::KOP * C::NP;
+  constexpr int KO = (NOP + 255) / 256;
+  constexpr int NS = C::EPB * C::NFN;   // face nodes of the block
+  constexpr int KF = (NS + 255) / 256;  // face nodes per thread
+  double opv[KO];
+#pragma unroll
+  for (int k = 0; k < KO; ++k) opv[k] = A.opT[tid + 256 * k < NOP ? tid + 256 * k : NOP - 1];
+  double gm[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + ecl];
+  double qv[kNsFields], Tv;
+  {
+    const int64_t idx = ecl * C::NP + ic;
+    load_state(A.q, Es, idx, qv);
+    Tv = A.T[idx];
+  }
+  double qpf[KF][kNsFields], Tpf[KF];
+  int ownf[KF];
+#pragma unroll
+  for (int u = 0; u < KF; ++u) {
+    const int s = tid + 256 * u < NS ? tid + 256 * u : NS - 1;
+    const int fl = s / C::NFN, fm = s - fl * C::NFN;
+    const int64_t ef = e0 + fl < A.E ? e0 + fl : A.E - 1;
+    const int face = fm / C::NFP, mm = fm - face * C::NFP;
+    const int2 cn = A.conn[face * A.Epad + ef];
+    const int jp = A.nbtab[(face * 24 + cn.y) * C::NFP + mm];
+    ownf[u] = A.fmask[fm];
+    const int64_t ip = static_cast<int64_t>(cn.x) * C::NP + jp;
+    load_state(A.q, Es, ip, qpf[u]);
+    Tpf[u] = A.T[ip];
+  }
+#pragma unroll
+  for (int k = 0; k < KO; ++k)
+    if (tid + 256 * k < NOP) s_op[tid + 256 * k] = opv[k];
   if (vol) {
     double v[kNsPrims];
     if (valid) {
-      double qq[kNsFields];
-      load_state(A.q, Es, e * C::NP + i, qq);
-      ns_primitives(qq, A.T[e * C::NP + i], v);
+      ns_primitives(qv, Tv, v);
     } else {
 #pragma unroll
       for (int c = 0; c < kNsPrims; ++c) v[c] = 0.0;
@@ -93,21 +148,17 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
     for (int c = 0; c < kNsPrims; ++c) s_v[el][c][i] = v[c];
   }
   __syncthreads();
-  for (int s = tid; s < C::EPB * C::NFN; s += blockDim.x) {
-    const int fl = s / C::NFN, fm = s - fl * C::NFN;
-    const int64_t ef = e0 + fl;
-    double dv[kNsPrims];
-    if (ef < A.E) {
-      const int face = fm / C::NFP, mm = fm - face * C::NFP;
-      const int2 cn = A.conn[face * A.Epad + ef];
-      const int jp = A.nbtab[(face * 24 + cn.y) * C::NFP + mm];
-      const int own = A.fmask[fm];
-      double qp[kNsFields], vp[kNsPrims];
-      const int64_t ip = static_cast<int64_t>(cn.x) * C::NP + jp;
-      load_state(A.q, Es, ip, qp);
-      ns_primitives(qp, A.T[ip], vp);
 #pragma unroll
-      for (int c = 0; c < kNsPrims; ++c) dv[c] = 0.5 * (vp[c] - s_v[fl][c][own]);
+  for (int u = 0; u < KF; ++u) {
+    const int s = tid + 256 * u;
+    if (s >= NS) break;
+    const int fl = s / C::NFN, fm = s - fl * C::NFN;
+    double dv[kNsPrims];
+    if (e0 + fl < A.E) {
+      double vp[kNsPrims];
+      ns_primitives(qpf[u], Tpf[u], vp);
+#pragma unroll
+      for (int c = 0; c < kNsPrims; ++c) dv[c] = 0.5 * (vp[c] - s_v[fl][c][ownf[u]]);
     } else {
 #pragma unroll
       for (int c = 0; c < kNsPrims; ++c) dv[c] = 0.0;
@@ -120,8 +171,6 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
   // (every thread runs the arithmetic, on clamped indices, so that all reach
   // the barriers below; only valid nodes are stored)
   double sg[kNsPrims][3];
-  const int elc = vol ? el : 0, ic = vol ? i : 0;
-  const int64_t ecl = e0 + elc < A.E ? e0 + elc : A.E - 1;
 #pragma unroll
   for (int c = 0; c < kNsPrims; ++c) sg[c][0] = sg[c][1] = sg[c][2] = 0.0;
 #pragma unroll 2
@@ -137,9 +186,6 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
       sg[c][2] = fma(dt, vj, sg[c][2]);
     }
   }
-  double gm[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + ecl];
 #pragma unroll
   for (int c = 0; c < kNsPrims; ++c) {
     const double wr = sg[c][0], ws = sg[c][1], wt = sg[c][2];
@@ -183,13 +229,11 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
 //   Delta = 1/2 (N.F(-) - N.F(+)) - 1/2 max(|U_N-| + c- |N|, |U_N+| + c+ |N|) (q- - q+),
 // F the total flux, N = Fscale n.
 template <int P>
-__device__ inline void ns_face_jump(const NsArgs& A, int64_t Es, int64_t ef, int fm, const double gm[9],
-                                    double D[kNsFields]) {
+__device__ inline void ns_face_jump(const NsArgs& A, int64_t Es, int64_t ef, int fm, int2 cn, int own,
+                                    const double gm[9], double D[kNsFields]) {
   using C = NsCfg<P>;
   const int face = fm / C::NFP, mm = fm - face * C::NFP;
-  const int2 cn = A.conn[face * A.Epad + ef];
   const int jp = A.nbtab[(face * 24 + cn.y) * C::NFP + mm];
-  const int own = A.fmask[fm];
   double N[3];
   scaled_normal(face, gm, N[0], N[1], N[2]);
   const double Fs = sqrt_pos(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
@@ -240,27 +284,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
   __shared__ double s_G[R::EPB][kNsFields][3][C::NP];
   __shared__ double s_D[R::EPB][kNsFields][C::NFN];
   const int tid = threadIdx.x;
-  for (int k = tid; k < C::KOP * C::NP; k += blockDim.x) s_op[k] = A.opT[k];
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * R::EPB;
   const int64_t Es = A.E * C::NP;
   const Transport tr{A.mu, A.Pr, A.Sc};
 
-  if (tid < R::EPB * C::NFN) {  // one face node
-    const int fl = tid / C::NFN, fm = tid - fl * C::NFN;
-    const int64_t ef = e0 + fl;
-    double D[kNsFields];
-    if (ef < A.E) {
-      double gm[9];
+  // the face node's connectivity, mask and metric are requested first, so
+  // they arrive while this thread's volume node is evaluated
+  const bool fnode = tid < R::EPB * C::NFN;
+  int2 fcn;
+  int fown;
+  double fgm[9];
+  {
+    const int s = fnode ? tid : 0;
+    const int fl = s / C::NFN, fm = s - fl * C::NFN;
+    const int64_t ef = e0 + fl < A.E ? e0 + fl : A.E - 1;
+    fcn = A.conn[(fm / C::NFP) * A.Epad + ef];
+    fown = A.fmask[fm];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) gm[k] = A.geo[k * A.Epad + ef];
-      ns_face_jump<P>(A, Es, ef, fm, gm, D);
-    } else {
-#pragma unroll
-      for (int f = 0; f < kNsFields; ++f) D[f] = 0.0;
-    }
-#pragma unroll
-    for (int f = 0; f < kNsFields; ++f) s_D[fl][f][fm] = D[f];
+    for (int k = 0; k < 9; ++k) fgm[k] = A.geo[k * A.Epad + ef];
   }
+  stage_block_array<C::KOP * C::NP, 256>(s_op, A.opT, tid);
   if (tid < R::NV) {  // one volume node
     const int el = tid / C::NP, i = tid - el * C::NP;
     const int64_t e = e0 + el;
@@ -286,6 +329,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
 #pragma unroll
         for (int f = 0; f < kNsFields; ++f) s_G[el][f][a][i] = 0.0;
     }
+  }
+  if (fnode) {  // one face node
+    const int fl = tid / C::NFN, fm = tid - fl * C::NFN;
+    const int64_t ef = e0 + fl;
+    double D[kNsFields];
+    if (ef < A.E) {
+      ns_face_jump<P>(A, Es, ef, fm, fcn, fown, fgm, D);
+    } else {
+#pragma unroll
+      for (int f = 0; f < kNsFields; ++f) D[f] = 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < kNsFields; ++f) s_D[fl][f][fm] = D[f];
   }
   __syncthreads();
   if (tid >= R::H * R::NV) return;
