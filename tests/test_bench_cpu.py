@@ -1,0 +1,48 @@
+"""Host-side pieces of the benchmark contract (no GPU): the one-GPU guard,
+the per-element algorithmic counts the roofline uses, and the gate that
+drops the stored HBM traffic once the kernel's sources differ from the ones
+the counters were taken on."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_algorithmic_counts_at_p3():
+    # 2 nf Np (3 Np + 4 Nfp) = 2 * 5 * 20 * 100 = 20,000 contraction flops,
+    # 52 * 20 pointwise and 80 * 40 face-flux flops; bytes: 2 * 5 * 20 * 8 +
+    # 72 (metric) + 32 (connectivity)
+    assert bench.algorithmic_counts(3) == (20000 + 1040 + 3200, 1704)
+    assert bench.algorithmic_counts(1) == (2 * 5 * 4 * (12 + 12) + 52 * 4 + 80 * 12, 2 * 5 * 4 * 8 + 104)
+
+
+def test_stored_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
+    got = bench.stored_traffic()
+    assert got is not None and got > 0  # the committed summary matches the sources
+    copies = []
+    for i, f in enumerate(bench.KERNEL_SRCS):
+        dst = tmp_path / f"src{i}"
+        shutil.copy(f, dst)
+        copies.append(dst)
+    monkeypatch.setattr(bench, "KERNEL_SRCS", [str(c) for c in copies])
+    assert bench.stored_traffic() == got
+    for c in copies:  # a change to any one source drops the stored figure
+        original = c.read_bytes()
+        c.write_bytes(original + b"\n// changed\n")
+        assert bench.stored_traffic() is None
+        c.write_bytes(original)
+        assert bench.stored_traffic() == got
