@@ -60,7 +60,9 @@ __global__ __launch_bounds__(256) void sources_kernel(MechTable mk, int64_t n, c
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
     double C[kMaxSpecies], w[kMaxSpecies];
-    for (int k = 0; k < mk.ns; ++k) C[k] = q[(5 + k) * n + i] * mk.invW[k];
+    // all loads of the node issued together (slots past ns are not used)
+#pragma unroll
+    for (int k = 0; k < kMaxSpecies; ++k) C[k] = q[(5 + (k < mk.ns ? k : mk.ns - 1)) * n + i] * mk.invW[k];
     node_sources(mk, C, 1.0 / T[i], w);
     for (int k = 0; k < mk.ns; ++k) omega[k * n + i] = w[k];
   }
