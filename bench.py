@@ -284,6 +284,8 @@ def reacting_leg(dg, wl, dev, stream, steps):
         dg.ns_rhs(mesh, th, q, T, sig, out, mech=mk, stream=stream)
         stream.synchronize()
         ms_T = _time_ms(stream, lambda: dg.temperature(th, q, T, it, stream=stream), steps)
+        omega = torch.empty((th.ns, mesh.E, mesh.Np), dtype=torch.float64, device=dev)
+        ms_src = _time_ms(stream, lambda: dg.sources(mk, q, T, omega, stream=stream), steps)
         ms_rhs = _time_ms(stream, lambda: dg.ns_rhs(mesh, th, q, T, sig, out, mech=mk, stream=stream), steps)
         work = torch.empty(dg.NS_WORK_PER_NODE * nn, dtype=torch.float64, device=dev)
         qs, Ts = q.clone(), T.clone()
@@ -300,7 +302,8 @@ def reacting_leg(dg, wl, dev, stream, steps):
            "mu": dg.MU, "Pr": dg.PR, "Sc": dg.SC,
            "ns_rhs_ms": round(ms_rhs, 4), "value": round(dof_f / (ms_rhs * 1e-3) / 1e9, 3),
            "unit": "GDOF·fields/s (gradient + right-hand side, sources included)",
-           "temperature_ms": round(ms_T, 4), "newton_mean_iters_from_1000K": round(float(iters.mean()), 3),
+           "temperature_ms": round(ms_T, 4), "sources_ms": round(ms_src, 4),
+           "newton_mean_iters_from_1000K": round(float(iters.mean()), 3),
            "newton_failures": int((iters < 0).sum()), "rk_step_ms": round(ms_rk, 4), "rk_dt": dt_rk,
            "finite": finite}
     return rec
