@@ -150,6 +150,35 @@ __device__ inline void stage_tile(double* sq, const double* __restrict__ q, int6
   __builtin_amdgcn_wave_barrier();
 }
 
+// The same copy through the LDS DMA path (global_load_lds_dwordx4): lane l of
+// a field's load k moves tile entries 2 (64 k + l) and 2 (64 k + l) + 1
+// straight into LDS, with no registers and no LDS write instructions.
+// Needs TQ and nval even, every field block 16-byte aligned in memory (q
+// 16-byte aligned; Es and base even) and, as measured, every LDS destination
+// base (sq + f TQ + 128 k) a multiple of 512 bytes: Np a multiple of 4.  Chunks at or past nval re-read
+// the last valid chunk, so every load stays inside the tile's valid entries
+// (their LDS slots are never read), and in a field's last, partial load the
+// lanes past the field's block are masked off.
+template <int TQ>
+__device__ inline void stage_tile_dma(double* sq, const double* __restrict__ q, int64_t Es, int64_t base, int nval,
+                                      int lane) {
+  static_assert(TQ % 64 == 0, "512-byte-aligned field blocks");
+  constexpr int NC = TQ / 2;          // chunks per field block
+  constexpr int KC = (NC + 63) / 64;  // loads per field
+  const int last = nval / 2 - 1;      // last valid chunk
+#pragma unroll
+  for (int f = 0; f < 5; ++f)
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = 64 * k + lane;
+      const double* src = q + f * Es + base + 2 * (c <= last ? c : last);
+      auto* dst = (__attribute__((address_space(3))) void*)(sq + f * TQ + 128 * k);
+      if (64 * k + 63 < NC || c < NC) __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+    }
+  __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): every chunk is in LDS
+  __builtin_amdgcn_wave_barrier();
+}
+
 // One entry of the fused 2N-storage Runge-Kutta stage
 //   res <- a res + dt rhs;  q_out <- q + b res
 // from values of res and q loaded beforehand (res_old is not used when
