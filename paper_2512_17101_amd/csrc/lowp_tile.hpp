@@ -132,9 +132,10 @@ __device__ inline void split_mma(const v8bf* __restrict__ op, int k, int lane, f
 // Runge-Kutta stage) of elements 16 tile .. 16 tile + 15.  `op` is the
 // operator table in the mode's layout, nb / fm the face tables.  With
 // STAGED, `sq` is this wave's LDS buffer of 5 x 16 Np doubles: the tile's
-// state is first copied there with coalesced loads, and own traces and
-// neighbour traces inside the tile are read from it.
-template <int P, int MODE, bool FUSED, bool STAGED = false>
+// state is first copied there with coalesced loads (with DMA, through the LDS
+// DMA path: Np a multiple of 4, q 16-byte aligned, sq 512-byte aligned), and
+// own traces and neighbour traces inside the tile are read from it.
+template <int P, int MODE, bool FUSED, bool STAGED = false, bool DMA = false>
 __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ s_op, const uint8_t* __restrict__ s_nb,
                                  const int* __restrict__ s_fm, int64_t tile, double* __restrict__ sq = nullptr) {
   using C = LCfg<P>;
@@ -146,7 +147,10 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
   const double gm1 = A.gamma - 1.0;
   const int64_t e0 = tile * 16;
   const int nval = static_cast<int>(A.E - e0 < 16 ? A.E - e0 : 16) * C::NP;
-  if constexpr (STAGED) stage_tile<TQ>(sq, q, Es, e0 * C::NP, nval, lane);
+  if constexpr (STAGED && DMA)
+    stage_tile_dma<TQ>(sq, q, Es, e0 * C::NP, nval, lane);
+  else if constexpr (STAGED)
+    stage_tile<TQ>(sq, q, Es, e0 * C::NP, nval, lane);
   {
     const int64_t e = e0 + n;
     const bool valid = e < A.E;

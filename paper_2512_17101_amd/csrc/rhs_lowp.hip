@@ -19,11 +19,11 @@ using namespace lowp;
 template <int P, int MODE>
 constexpr int lowp_wpe() { return P < 4 ? 3 : 2; }
 
-template <int P, int MODE, bool FUSED, int W>
+template <int P, int MODE, bool FUSED, int W, bool DMA>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lowp_wpe<P, MODE>()))) void rhs_euler_lowp_kernel(
     LowArgs A) {
   using C = LCfg<P>;
-  __shared__ double s_q[W][5 * 16 * C::NP];
+  __shared__ __align__(512) double s_q[W][5 * 16 * C::NP];  // 512-byte bases for the LDS DMA path
   __shared__ __align__(4) uint8_t s_nbl[lowp_lds_tables<P>() ? 4 * 24 * C::NFP : 4];
   __shared__ int s_fml[lowp_lds_tables<P>() ? 4 * C::NFP : 1];
   if constexpr (lowp_lds_tables<P>()) {
@@ -36,16 +36,27 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lowp_wpe
   const uint32_t* op = MODE == 1 ? reinterpret_cast<const uint32_t*>(A.op32) : reinterpret_cast<const uint32_t*>(A.opbf);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
   const int64_t tile = static_cast<int64_t>(blockIdx.x) * W + wave;
-  if (tile < A.ntiles) lowp_tile<P, MODE, FUSED, true>(A, op, s_nb, s_fm, tile, s_q[wave]);
+  if (tile < A.ntiles) lowp_tile<P, MODE, FUSED, true, DMA>(A, op, s_nb, s_fm, tile, s_q[wave]);
 }
 
+// The tile is staged through the LDS DMA path where Np is a multiple of 4
+// (p = 1, 3) and q is 16-byte aligned, as in the FP64 kernel.
 template <int P, int MODE, int W>
 void launch_lowp_pw(const Mesh& m, const LowArgs& args, bool fused, hipStream_t s) {
   const int blocks = static_cast<int>((m.Epad / 16 + W - 1) / W);
-  if (fused)
-    rhs_euler_lowp_kernel<P, MODE, true, W><<<blocks, 64 * W, 0, s>>>(args);
-  else
-    rhs_euler_lowp_kernel<P, MODE, false, W><<<blocks, 64 * W, 0, s>>>(args);
+  constexpr bool kDma = LCfg<P>::NP % 4 == 0;
+  const bool dma = kDma && (reinterpret_cast<uintptr_t>(args.q) & 15u) == 0;
+  if (dma) {
+    if (fused)
+      rhs_euler_lowp_kernel<P, MODE, true, W, kDma><<<blocks, 64 * W, 0, s>>>(args);
+    else
+      rhs_euler_lowp_kernel<P, MODE, false, W, kDma><<<blocks, 64 * W, 0, s>>>(args);
+  } else {
+    if (fused)
+      rhs_euler_lowp_kernel<P, MODE, true, W, false><<<blocks, 64 * W, 0, s>>>(args);
+    else
+      rhs_euler_lowp_kernel<P, MODE, false, W, false><<<blocks, 64 * W, 0, s>>>(args);
+  }
 }
 
 template <int P, int MODE>

@@ -281,8 +281,9 @@ def test_autotune_chooses_sets_and_caches(tmp_path):
     _check(c, out.cpu().numpy(), label="p=3 waves=2")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "split_bf16"])
 @pytest.mark.parametrize("order", [1, 2, 3])
-def test_state_staging_paths_agree_bitwise(order):
+def test_state_staging_paths_agree_bitwise(order, precision):
     """A state that is 16-byte aligned is staged into LDS by the DMA path (Np a
     multiple of 4: p = 1, 3), one that is only 8-byte aligned by register
     loads; both paths feed the same arithmetic, so the right-hand sides and a
@@ -300,13 +301,13 @@ def test_state_staging_paths_agree_bitwise(order):
     outs = []
     for q in (q_al, q_un):
         out = torch.empty_like(q_al)
-        dg.rhs(mesh, q, out)
+        dg.rhs(mesh, q, out, precision=precision)
         outs.append(out)
     torch.cuda.synchronize()
     assert torch.equal(outs[0], outs[1])
     dt = 1e-3
     work = torch.empty((2,) + tuple(q_al.shape), dtype=torch.float64, device=dev)
-    dg.rk_step(mesh, q_al, work, 0.0, dt)
-    dg.rk_step(mesh, q_un, work, 0.0, dt)
+    dg.rk_step(mesh, q_al, work, 0.0, dt, precision=precision)
+    dg.rk_step(mesh, q_un, work, 0.0, dt, precision=precision)
     torch.cuda.synchronize()
     assert torch.equal(q_al, q_un)
