@@ -23,8 +23,9 @@
  *    vertices v1=(-1,-1,-1), v2=(1,-1,-1), v3=(-1,1,-1), v4=(-1,-1,1); faces
  *    f0={t=-1}, f1={s=-1}, f2={r+s+t=-1}, f3={r=-1}.
  *  - Device buffers (q, rhs, work) are caller-owned device memory, 8-byte
- *    aligned at least (256-byte recommended); the library never frees them and
- *    keeps no pointer past return.  Compute calls are asynchronous on the given
+ *    aligned at least (256-byte recommended; at p = 1 and 3 a 16-byte-aligned
+ *    state lets the element kernels copy it into LDS by DMA, with the same
+ *    results); the library never frees them and keeps no pointer past return.  Compute calls are asynchronous on the given
  *    HIP stream (0 = the null stream); argument checks are synchronous.
  *  - Handles (dg_mesh, dg_thermo, dg_mech, dg_mlp, dg_batch) own their tables;
  *    *_destroy frees them.
