@@ -150,32 +150,51 @@ __device__ inline void stage_tile(double* sq, const double* __restrict__ q, int6
   __builtin_amdgcn_wave_barrier();
 }
 
-// The same copy through the LDS DMA path (global_load_lds_dwordx4): lane l of
-// a field's load k moves tile entries 2 (64 k + l) and 2 (64 k + l) + 1
-// straight into LDS, with no registers and no LDS write instructions.
-// Needs TQ and nval even, every field block 16-byte aligned in memory (q
-// 16-byte aligned; Es and base even) and, as measured, every LDS destination
-// base (sq + f TQ + 128 k) a multiple of 512 bytes: Np a multiple of 4.  Chunks at or past nval re-read
-// the last valid chunk, so every load stays inside the tile's valid entries
-// (their LDS slots are never read), and in a field's last, partial load the
-// lanes past the field's block are masked off.
+// The same copy with the LDS DMA path (global_load_lds_dwordx4) for the whole
+// 128-double groups of each field: lane l of group k moves entries
+// 128 k + 2 l and 128 k + 2 l + 1 straight into LDS, with no registers and no
+// LDS write instructions; the rest of the field (fewer than 128 entries) goes
+// through registers.  No DMA load sits under a lane-dependent condition:
+// with one there, the compiler merged DMA loads of different groups across
+// the branch and derived the LDS base (M0) from the first active lane's
+// value, which sent one group's data to another group's slots.  Needs TQ and
+// nval even, every field block 16-byte aligned in memory (q 16-byte aligned;
+// Es and base even) and, as measured, every LDS destination base
+// (sq + f TQ + 128 k) a multiple of 512 bytes: Np a multiple of 4.  Entries
+// at or past nval re-read the last valid ones (their LDS slots are never
+// read).
 template <int TQ>
 __device__ inline void stage_tile_dma(double* sq, const double* __restrict__ q, int64_t Es, int64_t base, int nval,
                                       int lane) {
   static_assert(TQ % 64 == 0, "512-byte-aligned field blocks");
-  constexpr int NC = TQ / 2;          // chunks per field block
-  constexpr int KC = (NC + 63) / 64;  // loads per field
-  const int last = nval / 2 - 1;      // last valid chunk
+  constexpr int KG = TQ / 128;        // whole 128-double groups per field
+  constexpr int R = TQ - 128 * KG;    // entries left to the register path
+  constexpr int KR = (R + 63) / 64;
+  const int last = nval / 2 - 1;      // last valid 16-byte chunk
+  double v[5][KR > 0 ? KR : 1];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const int c = 64 * k + lane;
+      const double* src = q + f * Es + base + 2 * (c <= last ? c : last);
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sq + f * TQ + 128 * k), 16, 0,
+                                       0);
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = 128 * KG + 64 * k + lane;
+      v[f][k] = q[f * Es + base + (i < nval ? i : nval - 1)];
+    }
+  }
 #pragma unroll
   for (int f = 0; f < 5; ++f)
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const int c = 64 * k + lane;
-      const double* src = q + f * Es + base + 2 * (c <= last ? c : last);
-      auto* dst = (__attribute__((address_space(3))) void*)(sq + f * TQ + 128 * k);
-      if (64 * k + 63 < NC || c < NC) __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+    for (int k = 0; k < KR; ++k) {
+      const int i = 128 * KG + 64 * k + lane;
+      if (i < R + 128 * KG && i < nval) sq[f * TQ + i] = v[f][k];
     }
-  __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): every chunk is in LDS
+  __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): every group is in LDS
   __builtin_amdgcn_wave_barrier();
 }
 

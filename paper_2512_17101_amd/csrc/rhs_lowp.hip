@@ -39,12 +39,14 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lowp_wpe
   if (tile < A.ntiles) lowp_tile<P, MODE, FUSED, true, DMA>(A, op, s_nb, s_fm, tile, s_q[wave]);
 }
 
-// The tile is staged through the LDS DMA path where Np is a multiple of 4
-// (p = 1, 3) and q is 16-byte aligned, as in the FP64 kernel.
+// FP32 contractions: the tile is staged through the LDS DMA path where Np is
+// a multiple of 4 (p = 1, 3) and q is 16-byte aligned, as in the FP64
+// kernel.  Split BF16 keeps register staging: with the DMA path its kernel
+// spills about 500 bytes per lane and runs at half speed.
 template <int P, int MODE, int W>
 void launch_lowp_pw(const Mesh& m, const LowArgs& args, bool fused, hipStream_t s) {
   const int blocks = static_cast<int>((m.Epad / 16 + W - 1) / W);
-  constexpr bool kDma = LCfg<P>::NP % 4 == 0;
+  constexpr bool kDma = LCfg<P>::NP % 4 == 0 && MODE == 1;
   const bool dma = kDma && (reinterpret_cast<uintptr_t>(args.q) & 15u) == 0;
   if (dma) {
     if (fused)
