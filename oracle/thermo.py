@@ -12,7 +12,8 @@ no law; the readings are:
 * temperature from (e, Y): Newton T_{n+1} = T_n - (e(T_n) - e) / cv(T_n),
   iterates clamped to [100, 6000] K, stop when |T_{n+1} - T_n| < tol and
   return T_{n+1} with iteration count n + 1; no convergence within max_iter
-  gives count -1;
+  gives count -1, and a step that the clamp cut short is never taken as
+  convergence (a root outside the interval is a failure, not the bound);
 * irreversible Arrhenius kinetics: k_j = A_j exp(-Ea_j / (R_u T)),
   r_j = k_j prod_k C_k^{nu'_kj}, C_k = rho Y_k / W_k,
   omega_k = W_k sum_j (nu''_kj - nu'_kj) r_j   [kg / (m^3 s)].
@@ -81,9 +82,11 @@ def newton_temperature(e, Y, th, T0, tol=1e-10, max_iter=50):
             break
         Ta = T[active]
         Ya = Y[:, active]
-        Tn = Ta - (mixture_e(Ta, Ya, th) - e[active]) / mixture_cv(Ta, Ya, th)
-        Tn = np.clip(Tn, T_MIN, T_MAX)
-        done = np.abs(Tn - Ta) < tol
+        Tu = Ta - (mixture_e(Ta, Ya, th) - e[active]) / mixture_cv(Ta, Ya, th)
+        Tn = np.clip(Tu, T_MIN, T_MAX)
+        # a step cut by the clamp is not convergence (the root would lie
+        # outside [T_MIN, T_MAX]); NaN compares false and never converges
+        done = (np.abs(Tn - Ta) < tol) & (Tn == Tu)
         T[active] = Tn
         idx = np.flatnonzero(active)
         iters[idx[done]] = n + 1

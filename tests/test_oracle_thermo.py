@@ -60,9 +60,28 @@ def test_forced_non_convergence_and_clamp():
     e = ot.mixture_e(rng.uniform(500, 2500, 100), Y, TH)
     _, it = ot.newton_temperature(e, Y, TH, 1000.0, max_iter=1)
     assert np.all(it == -1)
-    e_hot = ot.mixture_e(np.full(100, 9000.0), Y, TH)  # beyond the clamp
+    # roots beyond either end of the clamp interval: the iterate sits at the
+    # bound, and that is a failure (-1), not a converged temperature
+    e_hot = ot.mixture_e(np.full(100, 9000.0), Y, TH)
     T, it = ot.newton_temperature(e_hot, Y, TH, 1000.0)
-    assert np.all(T == ot.T_MAX) and np.all(it >= 1)
+    assert np.all(T == ot.T_MAX) and np.all(it == -1)
+    e_cold = ot.mixture_e(np.full(100, 40.0), Y, TH)
+    T, it = ot.newton_temperature(e_cold, Y, TH, 1000.0)
+    assert np.all(T == ot.T_MIN) and np.all(it == -1)
+    # a root just inside the bound still converges
+    e_in = ot.mixture_e(np.full(100, 5990.0), Y, TH)
+    T, it = ot.newton_temperature(e_in, Y, TH, 1000.0)
+    assert np.all(it >= 1)
+    np.testing.assert_allclose(T, 5990.0, rtol=0, atol=1e-8)
+
+
+def test_non_finite_state_fails():
+    Y = _random_Y(4, np.random.default_rng(5))
+    e = np.array([np.nan, np.inf, 1e6, 1e6])
+    Y[:, 3] = np.nan
+    T, it = ot.newton_temperature(e, Y, TH, 1000.0)
+    assert np.all(it[[0, 1, 3]] == -1) and it[2] >= 1
+    assert np.all(~np.isfinite(T[[0, 3]]))
 
 
 def test_arrhenius_log_linear():
