@@ -75,10 +75,19 @@ def rhs(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: float = GAMMA,
 
 
 def rhs_term_magnitude(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: float = GAMMA, elems=None):
-    """Magnitude of the terms summed into each RHS entry,
-    T_i = sum_a sum_j |D_a[i, j]| |G_{a,j}| + sum_{(f,m)} |LIFT[i, (f,m)]| |Delta_{(f,m)}|,
-    the scale of the floating-point dot-product error bound (Higham, Accuracy
-    and Stability of Numerical Algorithms, Sec. 3.1).  Same shape as rhs()."""
+    """Magnitude of the products summed into each RHS entry, taken before any
+    cancellation, the scale of the floating-point error bound of a computed
+    sum of products (Higham, Accuracy and Stability of Numerical Algorithms,
+    Sec. 3.1: |fl(sum x_k y_k) - sum x_k y_k| <= gamma_n sum |x_k y_k|):
+
+      T_i = sum_a sum_j |D_a[i, j]| sum_d |da/dx_d| |F_d(q_j)|
+            + sum_{(f,m)} |LIFT[i, (f,m)]| Fscale_f [ 1/2 sum_d |n_d| (|F_d(q-)| + |F_d(q+)|)
+                                                     + 1/2 lam (|q-| + |q+|) ].
+
+    The contravariant flux sum_d (da/dx_d) F_d and the face flux n.F(q-) -
+    n.F(q+) are themselves sums whose terms may cancel; their rounding is
+    relative to these absolute sums, not to the (smaller) results.  Same
+    shape as rhs()."""
     E = q.shape[1]
     idx = np.arange(E) if elems is None else np.asarray(elems, dtype=np.int64)
     qe = q[:, idx, :]
@@ -86,8 +95,8 @@ def rhs_term_magnitude(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: f
     rx = geo["rst_x"][idx]
     out = np.zeros_like(qe)
     for a, D in enumerate((ops["Dr"], ops["Ds"], ops["Dt"])):
-        G = rx[None, :, a, 0, None] * Fx + rx[None, :, a, 1, None] * Fy + rx[None, :, a, 2, None] * Fz
-        out += np.abs(G) @ np.abs(D).T
+        G = sum(np.abs(rx[None, :, a, d, None]) * np.abs(F) for d, F in enumerate((Fx, Fy, Fz)))
+        out += G @ np.abs(D).T
     Nfp = ops["Nfp"]
     fm = ops["Fmask"].reshape(-1)
     qM = qe[:, :, fm]
@@ -98,8 +107,17 @@ def rhs_term_magnitude(ops: dict, geo: dict, conn: dict, q: np.ndarray, gamma: f
     (FxP, FyP, FzP), (uP, vP, wP), cP = _fluxes(qP, gamma)
     nx, ny, nz = n[..., 0], n[..., 1], n[..., 2]
     lam = np.maximum(np.abs(uM * nx + vM * ny + wM * nz) + cM, np.abs(uP * nx + vP * ny + wP * nz) + cP)
-    delta = Fs * (0.5 * (nx * FxM + ny * FyM + nz * FzM - nx * FxP - ny * FyP - nz * FzP) - 0.5 * lam * (qM - qP))
-    return out + np.abs(delta) @ np.abs(ops["LIFT"]).T
+    face = Fs * (0.5 * (np.abs(nx) * (np.abs(FxM) + np.abs(FxP)) + np.abs(ny) * (np.abs(FyM) + np.abs(FyP))
+                        + np.abs(nz) * (np.abs(FzM) + np.abs(FzP))) + 0.5 * lam * (np.abs(qM) + np.abs(qP)))
+    return out + face @ np.abs(ops["LIFT"]).T
+
+
+def contraction_length(p: int) -> int:
+    """K = 3 Np + 4 Nfp: products summed into one RHS entry (volume terms of
+    three directions over Np nodes, lift terms over 4 Nfp face nodes)."""
+    Np = (p + 1) * (p + 2) * (p + 3) // 6
+    Nfp = (p + 1) * (p + 2) // 2
+    return 3 * Np + 4 * Nfp
 
 
 def max_wave_speed(q: np.ndarray, gamma: float = GAMMA) -> float:

@@ -56,6 +56,76 @@ def test_term_magnitude_bounds_rhs(mesh_p):
     np.testing.assert_allclose(oe.rhs_term_magnitude(ops, geo, conn, q, elems=idx), T[:, idx], rtol=1e-13)
 
 
+def _term_magnitude_brute_force(ops, geo, conn, q, e, i, gamma=oe.GAMMA):
+    """The same definition for one entry (all fields) by explicit loops over
+    every product, with the flux written out per field and direction."""
+    def flux(qq):
+        rho, m, E = qq[0], qq[1:4], qq[4]
+        u = m / rho
+        p = (gamma - 1.0) * (E - 0.5 * float(m @ u))
+        F = np.zeros((3, 5))
+        for d in range(3):
+            F[d, 0] = m[d]
+            for k in range(3):
+                F[d, 1 + k] = m[k] * u[d] + (p if k == d else 0.0)
+            F[d, 4] = (E + p) * u[d]
+        c = np.sqrt(gamma * p / rho)
+        return F, u, c
+
+    Np, Nfp = ops["Np"], ops["Nfp"]
+    out = np.zeros(5)
+    for a, D in enumerate((ops["Dr"], ops["Ds"], ops["Dt"])):
+        for j in range(Np):
+            F, _, _ = flux(q[:, e, j])
+            for d in range(3):
+                out += abs(D[i, j]) * abs(geo["rst_x"][e, a, d]) * np.abs(F[d])
+    for f in range(4):
+        nvec = geo["normals"][e, f]
+        for m in range(Nfp):
+            qm = q[:, e, ops["Fmask"][f, m]]
+            qp = q[:, conn["mapP_elem"][e, f * Nfp + m], conn["mapP_node"][e, f * Nfp + m]]
+            Fm, um, cm = flux(qm)
+            Fp, up, cp = flux(qp)
+            lam = max(abs(float(um @ nvec)) + cm, abs(float(up @ nvec)) + cp)
+            term = 0.5 * lam * (np.abs(qm) + np.abs(qp))
+            for d in range(3):
+                term = term + 0.5 * abs(nvec[d]) * (np.abs(Fm[d]) + np.abs(Fp[d]))
+            out += abs(ops["LIFT"][i, f * Nfp + m]) * geo["Fscale"][e, f] * term
+    return out
+
+
+def test_term_magnitude_equals_brute_force(mesh_p):
+    """Pins the error scale itself: an inflated (or deflated) T would make
+    every per-entry parity bar looser (or fail), so it must equal the sum of
+    absolute products written out term by term."""
+    ops, geo, conn, X = mesh_p
+    q = wl.vortex_state(X, pert=wl.density_perturbation(3))
+    q = q * (1.0 + 1e-2 * np.random.default_rng(4).standard_normal(q.shape))
+    T = oe.rhs_term_magnitude(ops, geo, conn, q)
+    for e, i in ((0, 0), (7, ops["Np"] - 1), (q.shape[1] - 1, ops["Np"] // 2)):
+        np.testing.assert_allclose(T[:, e, i], _term_magnitude_brute_force(ops, geo, conn, q, e, i), rtol=1e-13)
+
+
+def test_fp64_rhs_error_within_per_entry_bound(mesh_p):
+    """The FP64 oracle against the same evaluation in extended precision:
+    every entry's rounding error is within gamma_K T_i ~ K u T_i (Higham's
+    bound of a K-term sum of products, with the products' own rounding
+    relative to T); observed about one unit roundoff of T_i."""
+    ops, geo, conn, X = mesh_p
+    q = wl.vortex_state(X, pert=wl.density_perturbation(3))
+    q = q * (1.0 + 1e-2 * np.random.default_rng(5).standard_normal(q.shape))
+    r = oe.rhs(ops, geo, conn, q)
+    ld = np.longdouble
+    cast = lambda d: {k: (v.astype(ld) if isinstance(v, np.ndarray) and v.dtype == np.float64 else v)
+                      for k, v in d.items()}
+    r_ext = oe.rhs(cast(ops), cast(geo), conn, q.astype(ld), gamma=ld(oe.GAMMA)).astype(np.float64)
+    T = oe.rhs_term_magnitude(ops, geo, conn, q)
+    K = oe.contraction_length(ops["p"])
+    ratio = np.abs(r - r_ext) / T
+    assert ratio.max() <= K * 2.0 ** -53
+    assert ratio.max() <= 4 * 2.0 ** -53  # the observed scale, far inside the worst case
+
+
 def test_entropy_wave_linearity(mesh_p):
     ops, geo, conn, X = mesh_p
     vel = np.array([0.4, -0.25, 0.15])
