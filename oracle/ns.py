@@ -194,3 +194,102 @@ def temperature(q, th, T0=1000.0, tol=1e-10, max_iter=50):
     """Newton temperature of every node of q (thermo.newton_temperature)."""
     rho, u, v, w, e, Y = th_.primitives(q)
     return th_.newton_temperature(e, Y, th, T0, tol, max_iter)
+
+
+def gradient_term_magnitude(ops, geo, conn, v, elems=None):
+    """Sum of the absolute products in each lifted-gradient entry before
+    cancellation (Higham's error scale of a computed sum of products, as in
+    euler.rhs_term_magnitude):
+      sum_a |da/dx_d| (|D_a| |v|)_i + (|LIFT| (Fscale |n_d| (|v+| + |v-|) / 2))_i,
+    shaped like gradients()."""
+    ix = np.arange(v.shape[1]) if elems is None else np.asarray(elems)
+    Nfp = ops["Nfp"]
+    fm = ops["Fmask"].reshape(-1)
+    av = np.abs(v[:, ix])
+    Dv = [av @ np.abs(D).T for D in (ops["Dr"], ops["Ds"], ops["Dt"])]
+    tr = 0.5 * (np.abs(v[:, conn["mapP_elem"][ix], conn["mapP_node"][ix]]) + av[:, :, fm])
+    n = np.repeat(geo["normals"][ix], Nfp, axis=1)
+    Fs = np.repeat(geo["Fscale"][ix], Nfp, axis=1)
+    out = np.empty((3,) + av.shape)
+    for d in range(3):
+        out[d] = sum(np.abs(geo["rst_x"][ix][None, :, a, d, None]) * Dv[a] for a in range(3))
+        out[d] += (Fs * np.abs(n[..., d]) * tr) @ np.abs(ops["LIFT"]).T
+    return out
+
+
+def _viscous_flux_magnitude(q, T, smag, th, mu, Pr, Sc):
+    """|F^v| bound with every coefficient and gradient by its magnitude:
+    the viscous flux is linear in sigma, so its rounding (and the effect of
+    the gradients' own rounding) scales with these absolute sums."""
+    rho = q[0]
+    u = np.abs(q[1:4] / rho)
+    Y = q[5:] / rho
+    cp, _, _, hk = _mixture(T, Y, th)
+    g = smag[:, 0:3]
+    div = g[0, 0] + g[1, 1] + g[2, 2]
+    tau = np.empty((3, 3) + q.shape[1:])
+    for i in range(3):
+        for d in range(3):
+            tau[i, d] = mu * (g[d, i] + g[i, d]) + (mu * (2.0 / 3.0) * div if i == d else 0.0)
+    F = np.zeros((3,) + q.shape)
+    for d in range(3):
+        J = (mu / Sc) * smag[d, 4:]
+        for i in range(3):
+            F[d, 1 + i] = tau[i, d]
+        F[d, 4] = u[0] * tau[0, d] + u[1] * tau[1, d] + u[2] * tau[2, d] + (mu * cp / Pr) * smag[d, 3] \
+            + np.sum(np.abs(hk) * J, axis=0)
+        F[d, 5:] = J
+    return F
+
+
+def rhs_term_magnitude(ops, geo, conn, q, T, th, mech=None, mu=MU, Pr=PR, Sc=SC, elems=None):
+    """Sum of the absolute products in each right-hand-side entry before
+    cancellation, the scale of its rounding error (Higham, Sec. 3.1): the
+    volume and lift sums over |F^inv| + |F^v| with the viscous flux taken
+    from the gradients' own magnitudes (gradient_term_magnitude), the face
+    flux before its differences cancel, and for the sources
+    sum_j W_k |nu''_kj - nu'_kj| |r_j| (1 + Ea_j / (R_u T)): the rate's
+    exponential magnifies its argument's rounding by |Ea_j / (R_u T)|."""
+    ix = np.arange(q.shape[1]) if elems is None else np.asarray(elems)
+    Nfp = ops["Nfp"]
+    fm = ops["Fmask"].reshape(-1)
+    me, mn = conn["mapP_elem"][ix], conn["mapP_node"][ix]
+    S = np.unique(np.concatenate([ix, me.ravel()]))
+    sS = gradient_term_magnitude(ops, geo, conn, primitive_fields(q, T), elems=S)
+    sE = sS[:, :, np.searchsorted(S, ix)]
+    sP = sS[:, :, np.searchsorted(S, me), mn]
+    qE, TE = q[:, ix], T[ix]
+    Fi, _, _ = inviscid_flux(qE, TE, th)
+    AF = np.abs(Fi) + _viscous_flux_magnitude(qE, TE, sE, th, mu, Pr, Sc)
+    rx = geo["rst_x"][ix]
+    mag = np.zeros_like(qE)
+    for a, D in enumerate((ops["Dr"], ops["Ds"], ops["Dt"])):
+        mag += sum(np.abs(rx[None, :, a, d, None]) * AF[d] for d in range(3)) @ np.abs(D).T
+    qM, qP = qE[:, :, fm], q[:, me, mn]
+    TM, TP = TE[:, fm], T[me, mn]
+    FiM, uM, cM = inviscid_flux(qM, TM, th)
+    FiP, uP, cP = inviscid_flux(qP, TP, th)
+    AM = np.abs(FiM) + _viscous_flux_magnitude(qM, TM, sE[:, :, :, fm], th, mu, Pr, Sc)
+    AP = np.abs(FiP) + _viscous_flux_magnitude(qP, TP, sP, th, mu, Pr, Sc)
+    n = np.repeat(geo["normals"][ix], Nfp, axis=1)
+    Fs = np.repeat(geo["Fscale"][ix], Nfp, axis=1)
+    nd = [n[..., d] for d in range(3)]
+    lam = np.maximum(np.abs(sum(uM[d] * nd[d] for d in range(3))) + cM,
+                     np.abs(sum(uP[d] * nd[d] for d in range(3))) + cP)
+    face = Fs * (0.5 * sum(np.abs(nd[d]) * (AM[d] + AP[d]) for d in range(3))
+                 + 0.5 * lam * (np.abs(qM) + np.abs(qP)))
+    mag += face @ np.abs(ops["LIFT"]).T
+    if mech is not None:
+        K = len(th["W"])
+        rho = qE[0]
+        C = (rho.ravel()[None] * (qE[5:] / rho).reshape(K, -1)) / th["W"][:, None]
+        k = th_.rate_constants(TE, mech)
+        r = k.copy()
+        for j in range(len(mech["A"])):
+            for s_ in range(K):
+                if mech["nu_r"][j, s_]:
+                    r[j] = r[j] * C[s_] ** mech["nu_r"][j, s_]
+        cond = 1.0 + mech["Ea"][:, None] / (th_.R_U * TE.ravel()[None])
+        net = np.abs(mech["nu_p"] - mech["nu_r"]).T.astype(np.float64)
+        mag[5:] += (th["W"][:, None] * (net @ (np.abs(r) * cond))).reshape((K,) + TE.shape)
+    return mag

@@ -367,3 +367,45 @@ def test_element_subset_matches_the_whole_mesh():
     # a given whole-mesh sigma gives the same subset result
     r_giv = ns.rhs(ops, geo, conn, q, T, TH, MECH, sigma=s_all, elems=elems)
     assert np.all(np.abs(r_giv - r_all[:, elems]) <= 1e-13 * scale)
+
+
+def test_term_magnitudes_bound_the_extended_precision_error():
+    """The FP64 gradients and right-hand side against the same oracle in long
+    double: every entry's rounding error stays within K u times its term
+    magnitude (K = 3 Np + 4 Nfp), the per-entry parity scale of the GPU
+    tests; observed a few u.  The magnitudes also bound the results."""
+    TH_ = wl.synthetic_thermo(3003)
+    MECH_ = wl.synthetic_mechanism(3004)
+    ld = np.longdouble
+    cast = lambda d: {k: (v.astype(ld) if isinstance(v, np.ndarray) and v.dtype == np.float64 else v)
+                      for k, v in d.items()}
+    u = 2.0 ** -53
+    for p, dims in ((1, (3, 3, 4)), (3, (3, 3, 3))):
+        L_ = 0.01
+        xyz, vid = wl.kuhn_mesh(dims, (L_, L_, L_ * dims[2] / 3), 0.03, 1003)
+        ops = ore.operators(p)
+        geo = om.geometry(xyz)
+        conn = om.connectivity(vid, p)
+        X = om.node_coordinates(xyz, ops["rst"])
+        q = wl.reacting_state(X.reshape(-1, 3), seed=3005, L=L_, n_cells=3).reshape((12,) + X.shape[:2])
+        q = q * (1.0 + 1e-3 * np.random.default_rng(3005).standard_normal(q.shape))
+        T, it = ns.temperature(q, TH_)
+        assert np.all(it > 0)
+        K = 3 * ops["Np"] + 4 * ops["Nfp"]
+        v = ns.primitive_fields(q, T)
+        s64 = ns.gradients(ops, geo, conn, v)
+        sL = ns.gradients(cast(ops), cast(geo), conn, v.astype(ld)).astype(np.float64)
+        sm = ns.gradient_term_magnitude(ops, geo, conn, v)
+        assert np.all(np.abs(s64) <= sm * (1 + 1e-12))
+        assert (np.abs(s64 - sL) / sm).max() <= 4 * u
+        r64 = ns.rhs(ops, geo, conn, q, T, TH_, MECH_, sigma=s64)
+        rL = ns.rhs(cast(ops), cast(geo), conn, q.astype(ld), T.astype(ld), cast(TH_), cast(MECH_),
+                    sigma=sL.astype(ld)).astype(np.float64)
+        m = ns.rhs_term_magnitude(ops, geo, conn, q, T, TH_, MECH_)
+        assert np.all(np.abs(r64) <= m * (1 + 1e-12))
+        ratio = (np.abs(r64 - rL) / m).max()
+        assert ratio <= K * u
+        assert ratio <= 8 * u
+        idx = np.array([0, 4, len(xyz) - 1])
+        np.testing.assert_allclose(ns.rhs_term_magnitude(ops, geo, conn, q, T, TH_, MECH_, elems=idx), m[:, idx],
+                                   rtol=1e-13)
