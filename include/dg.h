@@ -62,12 +62,22 @@ struct dg_thermo_s;
 struct dg_mech_s;
 
 typedef struct {
-  int model;      /* 0 = Euler (ideal gas), 1 = reacting Navier-Stokes (dg_ns_*) */
+  int model;      /* 0 = Euler (ideal gas), 1 = reacting Navier-Stokes */
   double gamma;   /* Euler: ratio of specific heats, > 1 (unused by model 1) */
   double mu, Pr, Sc;                 /* model 1: viscosity [Pa s] >= 0, Prandtl and Schmidt numbers > 0 */
   const struct dg_thermo_s* thermo;  /* model 1: species thermodynamics (7 species), required */
   const struct dg_mech_s* mech;      /* model 1: reactions; NULL = no chemical sources */
+  /* model 1 through dg_rhs / dg_rk_step: caller-owned device scratch for the
+   * temperatures, Newton counts and lifted gradients (dg_rhs: at least
+   * DG_NS_RHS_WORK E Np doubles; dg_rk_step: DG_NS_STEP_WORK E Np), and the
+   * Newton tolerance [K] and step limit (<= 0 selects 1e-10 and 50).  The
+   * temperature solve starts from 1000 K.  Unused by model 0. */
+  double* work;
+  double tol;
+  int max_iter;
 } dg_params;
+#define DG_NS_RHS_WORK 35  /* T (1), Newton counts (1), lifted gradients (33) per node */
+#define DG_NS_STEP_WORK 59 /* T (1) + the dg_ns_rk_step scratch (58) per node */
 
 typedef struct dg_mesh_s* dg_mesh;
 
@@ -104,7 +114,8 @@ dg_status dg_mesh_nodes(dg_mesh m, double* xyz_host);
 dg_status dg_mesh_face_map(dg_mesh m, int64_t* nbr_elem, int32_t* nbr_node);
 dg_status dg_mesh_destroy(dg_mesh m);
 
-/* Strong-form nodal DG right-hand side of the Euler equations:
+/* Strong-form nodal DG right-hand side (the Euler benchmark of Sec. 5.2; the
+ * reacting flow of Sec. 5 with model 1).  Model 0, Euler:
  *   rhs = -sum_{a=r,s,t} D_a (sum_d da/dx_d F_d(q))
  *         + LIFT * ( Fscale * [ 1/2 n.(F(q-) - F(q+)) - 1/2 lam (q- - q+) ] )
  * with the local Lax-Friedrichs speed lam = max(|u-.n| + c-, |u+.n| + c+) at
@@ -113,15 +124,25 @@ dg_status dg_mesh_destroy(dg_mesh m);
  * operands rounded to FP32, FP32 accumulation); DG_SPLIT_BF16 (x = hi + lo
  * with hi = bf16(fp32(x)), lo = bf16(fp32(x) - hi), Op X ~ Op_hi X_hi +
  * Op_hi X_lo + Op_lo X_hi accumulated in FP32).  Fluxes, jumps and the
- * result are FP64 in every mode.  Asynchronous on `stream`. */
+ * result are FP64 in every mode.  Model 1, reacting Navier-Stokes (the
+ * equations of dg_ns_rhs below): q, rhs device [12][E][Np]; the temperature
+ * Newton solve (from 1000 K), the lifted gradients and the right-hand side
+ * with sources run in prm->work; DG_FP64 only (other precisions return
+ * DG_ERR_UNSUPPORTED).  A non-finite result raises the device's non-finite
+ * flag (dg_synchronize).  Asynchronous on `stream`. */
 dg_status dg_rhs(dg_mesh m, const dg_params* prm, dg_precision prec, const double* q, double* rhs,
                  hipStream_t stream);
 
 /* One step of Carpenter & Kennedy's five-stage fourth-order 2N-storage
- * Runge-Kutta scheme:  res <- 0; for s = 1..5: res <- a_s res + dt RHS(q);
+ * Runge-Kutta scheme (the paper's explicit RK4, Sec. 5.2, read as the
+ * low-storage form):  res <- 0; for s = 1..5: res <- a_s res + dt RHS(q);
  * q <- q + b_s res.  q: device [5][E][Np], updated in place.  work: device
  * scratch of at least 2 * 5 * E * Np doubles, caller-owned, contents
- * overwritten.  t is accepted for non-autonomous models (the Euler RHS does
+ * overwritten.  Model 1 (reacting Navier-Stokes, DG_FP64 only): q is
+ * [12][E][Np], work is unused and prm->work (DG_NS_STEP_WORK E Np doubles)
+ * holds the temperatures, whose solve starts from 1000 K at the first stage
+ * and from the previous stage's values after it (as dg_ns_rk_step).  A
+ * non-finite new state raises the device's non-finite flag.  t is accepted for non-autonomous models (the Euler RHS does
  * not depend on it).  With the mesh's launch configuration for prec (below)
  * each stage is one fused launch (RHS + stage update into a second state
  * buffer, then a final copy returns the state to q) or an RHS launch into
@@ -186,19 +207,38 @@ dg_status dg_mech_create(dg_thermo th, int n_reactions, const double* A, const d
                          const int32_t* nu_p, dg_mech* out);
 dg_status dg_mech_destroy(dg_mech m);
 
+struct dg_mlp_s;
+
 /* Temperature from the conserved state by Newton's method on
  * e(T; Y) = E/rho - |m|^2/(2 rho^2):  T <- T - (e(T) - e) / cv(T),
  * cv = sum Y_k (cp_k - R_k), iterates clamped to [100, 6000] K, stopping when
- * |T_{n+1} - T_n| < tol.  q: device [5+ns][n]; T_guess: device [n] initial
- * iterates, or NULL to start every point at T_default; T_out: device [n];
- * iters: device int32 [n], the step count, or -1 where max_iter steps did not
- * converge (T_out then holds the last iterate).  Asynchronous on `stream`. */
-dg_status dg_temperature(dg_thermo th, int64_t n, const double* q, const double* T_guess, double T_default,
-                         double* T_out, int32_t* iters, double tol, int max_iter, hipStream_t stream);
+ * |T_{n+1} - T_n| < tol (temperature-dependent thermochemistry of the
+ * reacting flow, Sec. 4 and 5).  q: device [5+ns][n]; T_guess: device [n]
+ * initial iterates, or NULL to start every point at 1000 K; T_out: device
+ * [n]; iters: device int32 [n], the step count, or -1 where max_iter steps did
+ * not converge (T_out then holds the last iterate).  A step cut by the clamp
+ * is never convergence, so a point whose root lies outside [100, 6000] K
+ * reports -1; a point whose state is not finite ends at once with -1 and a
+ * non-finite T.  Either failure raises the device's no-convergence or
+ * non-finite flag, which the next dg_synchronize returns as DG_ERR_NOCONV /
+ * DG_ERR_NONFINITE.  guess: a learned-guess network (see dg_mlp_*) or NULL;
+ * with it, T_guess must be NULL and the solve is that of
+ * dg_temperature_learned with at most 8 steps from the network's clamped
+ * prediction, then a restart from 1000 K.  Asynchronous on `stream`. */
+dg_status dg_temperature(int64_t n, const double* q, const double* T_guess, double* T_out, int32_t* iters,
+                         dg_thermo th, double tol, int max_iter, const struct dg_mlp_s* guess, hipStream_t stream);
 
 /* Species mass sources omega: device [ns][n] from q (device [5+ns][n]) and
- * T (device [n]).  Asynchronous on `stream`. */
-dg_status dg_sources(dg_mech mech, int64_t n, const double* q, const double* T, double* omega, hipStream_t stream);
+ * T (device [n]); the rates of dg_mech_create.  Asynchronous on `stream`. */
+dg_status dg_sources(int64_t n, const double* q, const double* T, double* omega, dg_mech mech, hipStream_t stream);
+
+/* Waits for `stream` on `device`, then reads and clears the device's failure
+ * flags: DG_ERR_NONFINITE if a kernel since the last call produced a
+ * non-finite state, right-hand side or temperature, else DG_ERR_NOCONV if a
+ * Newton solve ended with iteration count -1, else DG_OK.  The flags are one
+ * word per device shared by every stream and handle on it: a failure on any
+ * stream is reported by the next dg_synchronize on that device. */
+dg_status dg_synchronize(int device, hipStream_t stream);
 
 /* ---- learned temperature guess ------------------------------------------ */
 /* Multilayer perceptron x -> T0 with widths 9 -> 64 -> 64 -> 64 -> 1 and tanh

@@ -77,6 +77,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2))) v
     A.a = a;
     A.b = b;
     A.dt = L.dt[it.mesh];
+    A.flags = L.flags;
     const int p = M.p;
     const uint32_t* op = L.tabs.op[p];
     const uint8_t* nb = lds + L.tabs.nb_off[p];
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P < 4 ? 3 :
   A.a = a;
   A.b = b;
   A.dt = L.dt[it.mesh];
+  A.flags = L.flags;
   lowp_tile<P, MODE, true, true>(A, L.tabs.op[P], s_nb, s_fm, it.tile, s_q[wave]);
 }
 

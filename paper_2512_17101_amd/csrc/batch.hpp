@@ -49,6 +49,7 @@ struct BatchLaunch {
   int64_t p_begin[5], p_end[5];
   const double* dt;  // [n meshes]
   double gamma;
+  unsigned* flags;   // device failure flags (non-finite state)
   BatchTables tabs;
   int waves_per_block, blocks, xcd_chunks;
 };

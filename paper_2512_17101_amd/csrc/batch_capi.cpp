@@ -97,6 +97,7 @@ dg_status make_launch(const dg_batch_s& b, const dg_batch_config& c, double gamm
   }
   L.dt = b.dt;
   L.gamma = gamma;
+  L.flags = device_flags();
   L.tabs = b.tabs;
   L.waves_per_block = c.waves_per_block;
   L.blocks = static_cast<int>(blocks);

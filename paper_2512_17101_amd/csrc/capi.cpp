@@ -38,10 +38,15 @@ bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0
 
 dg_status check_params(const char* who, const dg_params* prm, dg_precision prec) {
   if (!prm) return fail(DG_ERR_ARG, std::string(who) + ": params is NULL");
-  if (prm->model != 0) return fail(DG_ERR_ARG, std::string(who) + ": only model 0 (Euler) is accepted");
-  if (!(prm->gamma > 1.0) || !std::isfinite(prm->gamma)) return fail(DG_ERR_ARG, std::string(who) + ": gamma must be > 1");
   if (prec != DG_FP64 && prec != DG_FP32 && prec != DG_SPLIT_BF16)
     return fail(DG_ERR_ARG, std::string(who) + ": unknown precision");
+  if (prm->model == 1) {
+    if (prec != DG_FP64)
+      return fail(DG_ERR_UNSUPPORTED, std::string(who) + ": the reacting model runs FP64 contractions only");
+    return DG_OK;
+  }
+  if (prm->model != 0) return fail(DG_ERR_ARG, std::string(who) + ": model must be 0 (Euler) or 1 (reacting NS)");
+  if (!(prm->gamma > 1.0) || !std::isfinite(prm->gamma)) return fail(DG_ERR_ARG, std::string(who) + ": gamma must be > 1");
   return DG_OK;
 }
 
@@ -70,6 +75,11 @@ extern "C" dg_status dg_rhs(dg_mesh h, const dg_params* prm, dg_precision prec, 
   if (st != DG_OK) return st;
   if (!q || !rhs || !aligned8(q) || !aligned8(rhs)) return fail(DG_ERR_ARG, "dg_rhs: null or misaligned state pointer");
   const Mesh& m = *reinterpret_cast<const Mesh*>(h);
+  if (prm->model == 1) {
+    DeviceGuard g(m.device);
+    if (!g.ok) return fail(DG_ERR_HIP, "dg_rhs: hipSetDevice failed");
+    return ns_rhs_model1(m, prm, q, rhs, stream);
+  }
   const size_t n = static_cast<size_t>(5) * m.E * m.Np;
   if (q == rhs || (rhs < q + n && q < rhs + n)) return fail(DG_ERR_ARG, "dg_rhs: q and rhs overlap");
   DeviceGuard g(m.device);
@@ -84,9 +94,15 @@ extern "C" dg_status dg_rk_step(dg_mesh h, const dg_params* prm, dg_precision pr
   if (!h) return fail(DG_ERR_ARG, "dg_rk_step: null mesh");
   dg_status st = check_params("dg_rk_step", prm, prec);
   if (st != DG_OK) return st;
-  if (!q || !work || !aligned8(q) || !aligned8(work)) return fail(DG_ERR_ARG, "dg_rk_step: null or misaligned pointer");
   if (!std::isfinite(dt)) return fail(DG_ERR_ARG, "dg_rk_step: dt must be finite");
   const Mesh& m = *reinterpret_cast<const Mesh*>(h);
+  if (prm->model == 1) {
+    if (!q || !aligned8(q)) return fail(DG_ERR_ARG, "dg_rk_step: null or misaligned pointer");
+    DeviceGuard g(m.device);
+    if (!g.ok) return fail(DG_ERR_HIP, "dg_rk_step: hipSetDevice failed");
+    return ns_step_model1(m, prm, q, dt, stream);
+  }
+  if (!q || !work || !aligned8(q) || !aligned8(work)) return fail(DG_ERR_ARG, "dg_rk_step: null or misaligned pointer");
   const size_t n = static_cast<size_t>(5) * m.E * m.Np;
   if (work < q + n && q < work + 2 * n) return fail(DG_ERR_ARG, "dg_rk_step: work overlaps q");
   DeviceGuard g(m.device);

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "internal.hpp"
+
 namespace dg {
 
 // Reciprocal and square root from the hardware approximations, refined by
@@ -202,11 +204,13 @@ __device__ inline void stage_tile_dma(double* sq, const double* __restrict__ q, 
 //   res <- a res + dt rhs;  q_out <- q + b res
 // from values of res and q loaded beforehand (res_old is not used when
 // a == 0: the first stage's residual buffer may hold anything).
-__device__ inline void stage_store(int64_t idx, double val, double res_old, double q_old, double* __restrict__ res,
-                                   double* __restrict__ qout, double a, double b, double dt) {
+__device__ inline double stage_store(int64_t idx, double val, double res_old, double q_old, double* __restrict__ res,
+                                     double* __restrict__ qout, double a, double b, double dt) {
   const double r = (a == 0.0 ? 0.0 : a * res_old) + dt * val;
+  const double qn = q_old + b * r;
   res[idx] = r;
-  qout[idx] = q_old + b * r;
+  qout[idx] = qn;
+  return qn;
 }
 
 // Writes one tile's outputs staged in this wave's LDS buffer (field f's
@@ -216,11 +220,12 @@ __device__ inline void stage_store(int64_t idx, double val, double res_old, doub
 // and q value of a round of fields is loaded before the round's first
 // store: the compiler cannot rule out that a store to res or qout aliases a
 // later load, so entry-by-entry code would wait out one memory latency per
-// entry.
+// entry.  A non-finite value among the stored ones (the right-hand side, or
+// the new state of a fused stage) raises the device's non-finite flag.
 template <bool FUSED, int TQ>
 __device__ inline void store_tile(const double* sq, int nval, int64_t base, int64_t Es, int lane,
                                   double* __restrict__ rhs, double* __restrict__ res, double* __restrict__ qout,
-                                  const double* __restrict__ q, double a, double b, double dt) {
+                                  const double* __restrict__ q, double a, double b, double dt, unsigned* flags) {
   constexpr int KN = (TQ + 63) / 64;
   constexpr int FG = tile_round_fields<TQ>();
   // an opaque copy of the tile offset: otherwise the compiler shares these
@@ -231,13 +236,18 @@ __device__ inline void store_tile(const double* sq, int nval, int64_t base, int6
     asm volatile("" : "+v"(lo), "+v"(hi));
     base = (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
   }
+  bool bad = false;
   if constexpr (!FUSED) {
 #pragma unroll
     for (int f = 0; f < 5; ++f)
 #pragma unroll
       for (int k = 0; k < KN; ++k) {
         const int i = 64 * k + lane;
-        if (i < nval) rhs[f * Es + base + i] = sq[f * TQ + i];
+        if (i < nval) {
+          const double v = sq[f * TQ + i];
+          bad |= nonfinite(v);
+          rhs[f * Es + base + i] = v;
+        }
       }
   } else {
 #pragma unroll
@@ -259,10 +269,12 @@ __device__ inline void store_tile(const double* sq, int nval, int64_t base, int6
         for (int k = 0; k < KN; ++k) {
           const int i = 64 * k + lane;
           if (f0 + ff < 5 && i < nval)
-            stage_store((f0 + ff) * Es + base + i, sq[(f0 + ff) * TQ + i], rv[ff][k], qv[ff][k], res, qout, a, b, dt);
+            bad |= nonfinite(stage_store((f0 + ff) * Es + base + i, sq[(f0 + ff) * TQ + i], rv[ff][k], qv[ff][k], res,
+                                         qout, a, b, dt));
         }
     }
   }
+  raise_flag(flags, bad, kFlagNonFinite);
 }
 
 }  // namespace dg

@@ -15,6 +15,20 @@ namespace dg {
 dg_status fail(dg_status s, const std::string& msg);
 dg_status hip_fail(hipError_t e, const char* what);
 
+// Device-side failure flags: one word per device, OR-ed by kernels and read
+// (and cleared) by dg_synchronize.
+constexpr unsigned kFlagNoConv = 1u;     // a Newton solve ended without converging
+constexpr unsigned kFlagNonFinite = 2u;  // a non-finite value was produced
+// Address of the current device's flag word (the device must be current).
+unsigned* device_flags();
+
+// True for NaN and +-Inf.
+__device__ inline bool nonfinite(double v) { return !(__builtin_fabs(v) <= 1.7976931348623157e308); }
+// One atomic OR per lane that saw a failure (none in the normal case).
+__device__ inline void raise_flag(unsigned* flags, bool bad, unsigned bit) {
+  if (bad && flags) atomicOr(flags, bit);
+}
+
 // Low-storage five-stage fourth-order Runge-Kutta coefficients
 // (Carpenter & Kennedy 1994): res <- A_s res + dt rhs, q <- q + B_s res.
 extern const double kLsrkA[5];
@@ -106,6 +120,9 @@ dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, 
                                 hipStream_t s);
 dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,
                              double* q, hipStream_t s);
+// dg_rhs / dg_rk_step with model 1 (reacting Navier-Stokes), prm->work scratch.
+dg_status ns_rhs_model1(const Mesh& m, const dg_params* prm, const double* q, double* rhs, hipStream_t s);
+dg_status ns_step_model1(const Mesh& m, const dg_params* prm, double* q, double dt, hipStream_t s);
 // q[f][n] <- v[f] for f < 5 (a uniform state).
 dg_status launch_fill_state(double* q, int64_t n, const double v[5], hipStream_t s);
 

@@ -82,6 +82,7 @@ struct LowArgs {
   int64_t E, Epad;
   int ntiles;
   double gamma, a, b, dt;
+  unsigned* flags;  // device failure flags (non-finite output); may be null
 };
 
 // Lane (n, g) holds in register i the k = g (mod 4) part of row i of a 4-row
@@ -344,9 +345,10 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
             }
       }
       __builtin_amdgcn_wave_barrier();
-      store_tile<FUSED, TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
+      store_tile<FUSED, TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt, A.flags);
     } else if constexpr (!FUSED) {
       if (valid) {
+        bool bad = false;
 #pragma unroll
         for (int f = 0; f < 5; ++f)
 #pragma unroll
@@ -354,10 +356,16 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int row = out_row(rb, v);
-              if (row < C::NP) A.rhs[f * Es + e * C::NP + row] = static_cast<double>(acc[f][rb][v]);
+              if (row < C::NP) {
+                const double val = static_cast<double>(acc[f][rb][v]);
+                bad |= nonfinite(val);
+                A.rhs[f * Es + e * C::NP + row] = val;
+              }
             }
+        raise_flag(A.flags, bad, kFlagNonFinite);
       }
     } else if (valid) {
+      bool bad = false;
       // one field per round: its res and q loads all issued before its stores
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
@@ -377,10 +385,11 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
           for (int v = 0; v < 4; ++v) {
             const int row = out_row(rb, v);
             if (row < C::NP)
-              stage_store(f * Es + e * C::NP + row, static_cast<double>(acc[f][rb][v]), rv[rb][v], qv[rb][v], A.res,
-                          A.qout, A.a, A.b, A.dt);
+              bad |= nonfinite(stage_store(f * Es + e * C::NP + row, static_cast<double>(acc[f][rb][v]), rv[rb][v],
+                                           qv[rb][v], A.res, A.qout, A.a, A.b, A.dt));
           }
       }
+      raise_flag(A.flags, bad, kFlagNonFinite);
     }
   }
 }

@@ -1,5 +1,6 @@
 // Pointwise stage of the 2N-storage Runge-Kutta scheme, FP64:
 //   res <- a res + dt rhs;  q <- q + b res.
+// A non-finite new state raises the device's non-finite flag.
 // A stage with a = 0 does not read res (it may hold anything).
 #include "internal.hpp"
 
@@ -8,13 +9,17 @@ namespace {
 
 __global__ __launch_bounds__(256) void lsrk_update_kernel(int64_t n, double a, double b, double dt,
                                                           const double* __restrict__ rhs, double* __restrict__ res,
-                                                          double* __restrict__ q) {
+                                                          double* __restrict__ q, unsigned* flags) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  bool bad = false;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double r = (a == 0.0 ? 0.0 : a * res[i]) + dt * rhs[i];
+    const double qn = q[i] + b * r;
+    bad |= nonfinite(qn);
     res[i] = r;
-    q[i] = q[i] + b * r;
+    q[i] = qn;
   }
+  raise_flag(flags, bad, kFlagNonFinite);
 }
 
 struct Five {
@@ -46,7 +51,7 @@ dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const dou
   const int64_t threads = 256;
   int64_t blocks = (n + threads - 1) / threads;
   if (blocks > 256 * 64) blocks = 256 * 64;
-  lsrk_update_kernel<<<static_cast<unsigned>(blocks), threads, 0, s>>>(n, a, b, dt, rhs, res, q);
+  lsrk_update_kernel<<<static_cast<unsigned>(blocks), threads, 0, s>>>(n, a, b, dt, rhs, res, q, device_flags());
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

@@ -433,7 +433,9 @@ __global__ __launch_bounds__(256) void temperature_learned_kernel(ThermoTable th
                                                                   double* __restrict__ Tout,
                                                                   int32_t* __restrict__ iters, double tol,
                                                                   int max_iter, int learned_max_iter,
-                                                                  int32_t* __restrict__ fallback_count) {
+                                                                  int32_t* __restrict__ fallback_count,
+                                                                  unsigned* flags) {
+  bool noconv = false, bad = false;
   const int lane = threadIdx.x & 63;
   const int ln = lane & 15, g = lane >> 4;
   const int64_t groups = (n + 63) / 64;
@@ -478,13 +480,19 @@ __global__ __launch_bounds__(256) void temperature_learned_kernel(ThermoTable th
 #pragma unroll
       for (int m = 0; m < 5; ++m) Bc[m] += cc * th.cp[k][m];
     }
+    // the same Newton iteration as the plain solve (a clamped step is not
+    // convergence; a non-finite iterate ends the solve)
     auto solve = [&](double T, int limit, int& steps) {
       for (int s = 1; s <= limit; ++s) {
         const double eT = T * (Bh[0] + T * (Bh[1] + T * (Bh[2] + T * (Bh[3] + T * Bh[4])))) + Bh[5] - cR * T;
         const double cv = Bc[0] + T * (Bc[1] + T * (Bc[2] + T * (Bc[3] + T * Bc[4]))) - cR;
-        double Tn = T - (eT - e) / cv;
-        Tn = fmin(fmax(Tn, kTmin), kTmax);
-        const bool done = fabs(Tn - T) < tol;
+        const double Tu = T - (eT - e) / cv;
+        if (nonfinite(Tu)) {
+          steps = -1;
+          return Tu;
+        }
+        const double Tn = fmin(fmax(Tu, kTmin), kTmax);
+        const bool done = fabs(Tn - T) < tol && Tn == Tu;
         T = Tn;
         if (done) { steps = s; return T; }
       }
@@ -492,8 +500,8 @@ __global__ __launch_bounds__(256) void temperature_learned_kernel(ThermoTable th
       return T;
     };
     double T0 = static_cast<double>(pred) * V.norm.T_std + V.norm.T_mean;
+    if (nonfinite(T0)) T0 = Tdefault;  // tested before the clamp, which would turn NaN into Tmin
     T0 = fmin(fmax(T0, kTmin), kTmax);
-    if (!(T0 == T0)) T0 = Tdefault;
     int steps = 0;
     double T = solve(T0, learned_max_iter, steps);
     int total = steps;
@@ -503,9 +511,13 @@ __global__ __launch_bounds__(256) void temperature_learned_kernel(ThermoTable th
       T = solve(Tdefault, max_iter, s2);
       total = s2 < 0 ? -1 : learned_max_iter + s2;
     }
+    noconv |= total < 0;
+    bad |= nonfinite(T);
     Tout[i] = T;
     iters[i] = total;
   }
+  raise_flag(flags, noconv, kFlagNoConv);
+  raise_flag(flags, bad, kFlagNonFinite);
 }
 
 // Sums of the raw features, the temperature and their squares over the
@@ -612,7 +624,8 @@ dg_status launch_temperature_learned(const ThermoTable& th, const MlpView& v, in
                                      double T_default, double* T_out, int32_t* iters, double tol, int max_iter,
                                      int learned_max_iter, int32_t* fallback_count, hipStream_t s) {
   temperature_learned_kernel<<<stream_grid((n + 63) / 64), 256, 0, s>>>(th, v, n, q, T_default, T_out, iters, tol,
-                                                                         max_iter, learned_max_iter, fallback_count);
+                                                                         max_iter, learned_max_iter, fallback_count,
+                                                                         device_flags());
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

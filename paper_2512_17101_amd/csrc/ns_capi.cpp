@@ -84,21 +84,13 @@ extern "C" dg_status dg_ns_rhs(dg_mesh h, const dg_params* prm, const double* q,
   return launch_ns_rhs(m.p, A, false, stream);
 }
 
-extern "C" dg_status dg_ns_rk_step(dg_mesh h, const dg_params* prm, double* q, double* T, double* work, double dt,
-                                   double tol, int max_iter, hipStream_t stream) {
-  if (!h) return fail(DG_ERR_ARG, "dg_ns_rk_step: null mesh");
-  const Mesh& m = *reinterpret_cast<const Mesh*>(h);
-  dg_status st = check("dg_ns_rk_step", m, prm);
-  if (st != DG_OK) return st;
-  if (!q || !T || !work || !aligned8(q) || !aligned8(T) || !aligned8(work))
-    return fail(DG_ERR_ARG, "dg_ns_rk_step: null or misaligned pointer");
-  if (!std::isfinite(dt)) return fail(DG_ERR_ARG, "dg_ns_rk_step: dt must be finite");
-  if (!(tol > 0.0) || max_iter < 1) return fail(DG_ERR_ARG, "dg_ns_rk_step: need tol > 0 and max_iter >= 1");
+namespace {
+
+// One LSRK(5,4) step of the reacting system; T holds the first stage's Newton
+// start (T_valid) or is filled from the plain start; work: 58 E Np doubles.
+dg_status ns_step(const Mesh& m, const dg_params* prm, double* q, double* T, bool T_valid, double* work, double dt,
+                  double tol, int max_iter, hipStream_t stream) {
   const size_t n = static_cast<size_t>(m.E) * m.Np;
-  if (overlap(work, 58 * n, q, kFields * n) || overlap(work, 58 * n, T, n) || overlap(q, kFields * n, T, n))
-    return fail(DG_ERR_ARG, "dg_ns_rk_step: q, T and work must not overlap");
-  DeviceGuard g(m.device);
-  if (!g.ok) return fail(DG_ERR_HIP, "dg_ns_rk_step: hipSetDevice failed");
   double* res = work;
   double* buf[2] = {q, work + kFields * n};
   double* sigma = work + 2 * kFields * n;
@@ -114,7 +106,8 @@ extern "C" dg_status dg_ns_rk_step(dg_mesh h, const dg_params* prm, double* q, d
     A.qout = buf[(s + 1) & 1];
     A.a = kLsrkA[s];
     A.b = kLsrkB[s];
-    st = launch_temperature(th, static_cast<int64_t>(n), A.q, T, 1000.0, T, iters, tol, max_iter, stream);
+    dg_status st = launch_temperature(th, static_cast<int64_t>(n), A.q, (s > 0 || T_valid) ? T : nullptr, kTdefault, T,
+                                      iters, tol, max_iter, stream);
     if (st != DG_OK) return st;
     st = launch_ns_gradients(m.p, A, stream);
     if (st != DG_OK) return st;
@@ -124,3 +117,70 @@ extern "C" dg_status dg_ns_rk_step(dg_mesh h, const dg_params* prm, double* q, d
   DG_HIP(hipMemcpyAsync(q, buf[1], kFields * n * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return DG_OK;
 }
+
+double newton_tol(const dg_params* prm) { return prm->tol > 0.0 ? prm->tol : 1e-10; }
+int newton_max_iter(const dg_params* prm) { return prm->max_iter > 0 ? prm->max_iter : 50; }
+
+}  // namespace
+
+extern "C" dg_status dg_ns_rk_step(dg_mesh h, const dg_params* prm, double* q, double* T, double* work, double dt,
+                                   double tol, int max_iter, hipStream_t stream) {
+  if (!h) return fail(DG_ERR_ARG, "dg_ns_rk_step: null mesh");
+  const Mesh& m = *reinterpret_cast<const Mesh*>(h);
+  dg_status st = check("dg_ns_rk_step", m, prm);
+  if (st != DG_OK) return st;
+  if (!q || !T || !work || !aligned8(q) || !aligned8(T) || !aligned8(work))
+    return fail(DG_ERR_ARG, "dg_ns_rk_step: null or misaligned pointer");
+  if (!std::isfinite(dt)) return fail(DG_ERR_ARG, "dg_ns_rk_step: dt must be finite");
+  if (!(tol > 0.0) || max_iter < 1) return fail(DG_ERR_ARG, "dg_ns_rk_step: need tol > 0 and max_iter >= 1");
+  const size_t n = static_cast<size_t>(m.E) * m.Np;
+  if (overlap(work, 58 * n, q, kFields * n) || overlap(work, 58 * n, T, n) || overlap(q, kFields * n, T, n))
+    return fail(DG_ERR_ARG, "dg_ns_rk_step: q, T and work must not overlap");
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_ns_rk_step: hipSetDevice failed");
+  return ns_step(m, prm, q, T, true, work, dt, tol, max_iter, stream);
+}
+
+namespace dg {
+
+// dg_rhs with model 1: Newton temperatures from 1000 K, lifted gradients and
+// the right-hand side, all scratch in prm->work (DG_NS_RHS_WORK E Np doubles:
+// T, Newton counts, gradients).
+dg_status ns_rhs_model1(const Mesh& m, const dg_params* prm, const double* q, double* rhs, hipStream_t stream) {
+  dg_status st = check("dg_rhs", m, prm);
+  if (st != DG_OK) return st;
+  const size_t n = static_cast<size_t>(m.E) * m.Np;
+  double* w = prm->work;
+  if (!w || !aligned8(w)) return fail(DG_ERR_ARG, "dg_rhs: model 1 needs params.work (35 E Np doubles)");
+  if (overlap(w, DG_NS_RHS_WORK * n, q, kFields * n) || overlap(w, DG_NS_RHS_WORK * n, rhs, kFields * n) ||
+      overlap(q, kFields * n, rhs, kFields * n))
+    return fail(DG_ERR_ARG, "dg_rhs: q, rhs and params.work must not overlap");
+  double* T = w;
+  int32_t* iters = reinterpret_cast<int32_t*>(w + n);
+  double* sigma = w + 2 * n;
+  st = launch_temperature(thermo_table(prm->thermo), static_cast<int64_t>(n), q, nullptr, kTdefault, T, iters,
+                          newton_tol(prm), newton_max_iter(prm), stream);
+  if (st != DG_OK) return st;
+  NsArgs A = make_args(m, prm);
+  A.q = q;
+  A.T = T;
+  A.sigma = sigma;
+  A.rhs = rhs;
+  st = launch_ns_gradients(m.p, A, stream);
+  if (st != DG_OK) return st;
+  return launch_ns_rhs(m.p, A, false, stream);
+}
+
+// dg_rk_step with model 1: prm->work holds T (E Np) and the step scratch.
+dg_status ns_step_model1(const Mesh& m, const dg_params* prm, double* q, double dt, hipStream_t stream) {
+  dg_status st = check("dg_rk_step", m, prm);
+  if (st != DG_OK) return st;
+  const size_t n = static_cast<size_t>(m.E) * m.Np;
+  double* w = prm->work;
+  if (!w || !aligned8(w)) return fail(DG_ERR_ARG, "dg_rk_step: model 1 needs params.work (59 E Np doubles)");
+  if (overlap(w, DG_NS_STEP_WORK * n, q, kFields * n))
+    return fail(DG_ERR_ARG, "dg_rk_step: q and params.work must not overlap");
+  return ns_step(m, prm, q, w, false, w + n, dt, newton_tol(prm), newton_max_iter(prm), stream);
+}
+
+}  // namespace dg

@@ -54,6 +54,7 @@ struct RhsArgs {
   int ntiles;
   int dma;  // q is 16-byte aligned: the LDS DMA staging kernel may be used
   double gamma, a, b, dt;
+  unsigned* flags;  // device failure flags (non-finite output)
 };
 
 // Waves (tiles) per block W: the per-wave state tile lives in LDS (5 fields
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ?
     }
   }
   __builtin_amdgcn_wave_barrier();
-  store_tile<FUSED, TL::TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt);
+  store_tile<FUSED, TL::TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt, A.flags);
 }
 
 template <int P, int W>
@@ -274,6 +275,7 @@ dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, do
   A.a = a;
   A.b = b;
   A.dt = dt;
+  A.flags = device_flags();
   switch (m.p) {
     case 1: return launch_p<1>(m, A, fused, s);
     case 2: return launch_p<2>(m, A, fused, s);

@@ -122,6 +122,7 @@ dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, 
   A.a = a;
   A.b = b;
   A.dt = dt;
+  A.flags = device_flags();
   if (prec == DG_FP32) return launch_mode<1>(m, A, fused, s);
   if (prec == DG_SPLIT_BF16) return launch_mode<2>(m, A, fused, s);
   return fail(DG_ERR_ARG, "rhs: unknown precision");

@@ -8,7 +8,10 @@
 // are polynomials in T whose coefficients are formed once per node, so each
 // Newton step T <- T - (e(T) - e) / cv(T) is two Horner evaluations.
 // Iterates are clamped to [100, 6000] K; the step count is returned, or -1
-// when |T_{n+1} - T_n| < tol is not reached within max_iter steps.
+// when |T_{n+1} - T_n| < tol is not reached within max_iter steps (a step cut
+// by the clamp never counts as converged).  A point without a root to find
+// (non-finite iterate) ends at once with -1 and a non-finite T.  Failures
+// raise the device's no-convergence / non-finite flags.
 //
 // Sources: C_k = rho Y_k / W_k, k_j = A_j exp(-Ea_j / (R_u T)),
 // r_j = k_j prod_k C_k^{nu'_kj}, omega_k = W_k sum_j (nu''_kj - nu'_kj) r_j.
@@ -21,8 +24,9 @@ namespace {
 __global__ __launch_bounds__(256) void temperature_kernel(ThermoTable th, int64_t n, const double* __restrict__ q,
                                                           const double* __restrict__ Tguess, double Tdefault,
                                                           double* __restrict__ Tout, int32_t* __restrict__ iters,
-                                                          double tol, int max_iter) {
+                                                          double tol, int max_iter, unsigned* flags) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  bool noconv = false, bad = false;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double rho = q[i];
     const double ir = 1.0 / rho;
@@ -44,15 +48,25 @@ __global__ __launch_bounds__(256) void temperature_kernel(ThermoTable th, int64_
     for (int s = 1; s <= max_iter; ++s) {
       const double eT = T * (Bh[0] + T * (Bh[1] + T * (Bh[2] + T * (Bh[3] + T * Bh[4])))) + Bh[5] - cR * T;
       const double cv = Bc[0] + T * (Bc[1] + T * (Bc[2] + T * (Bc[3] + T * Bc[4]))) - cR;
-      double Tn = T - (eT - e) / cv;
-      Tn = fmin(fmax(Tn, kTmin), kTmax);
-      const bool done = fabs(Tn - T) < tol;
+      const double Tu = T - (eT - e) / cv;
+      if (nonfinite(Tu)) {  // non-finite state or guess: no root to find
+        T = Tu;
+        bad = true;
+        break;
+      }
+      const double Tn = fmin(fmax(Tu, kTmin), kTmax);
+      // a step that had to be clamped is not convergence: a root outside
+      // [Tmin, Tmax] would otherwise be reported as the clamp bound
+      const bool done = fabs(Tn - T) < tol && Tn == Tu;
       T = Tn;
       if (done) { it = s; break; }
     }
+    noconv |= it < 0;
     Tout[i] = T;
     iters[i] = it;
   }
+  raise_flag(flags, noconv, kFlagNoConv);
+  raise_flag(flags, bad, kFlagNonFinite);
 }
 
 __global__ __launch_bounds__(256) void sources_kernel(MechTable mk, int64_t n, const double* __restrict__ q,
@@ -78,7 +92,8 @@ int grid_for(int64_t n) {
 
 dg_status launch_temperature(const ThermoTable& th, int64_t n, const double* q, const double* Tguess, double Tdefault,
                              double* Tout, int32_t* iters, double tol, int max_iter, hipStream_t s) {
-  temperature_kernel<<<grid_for(n), 256, 0, s>>>(th, n, q, Tguess, Tdefault, Tout, iters, tol, max_iter);
+  temperature_kernel<<<grid_for(n), 256, 0, s>>>(th, n, q, Tguess, Tdefault, Tout, iters, tol, max_iter,
+                                                  device_flags());
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

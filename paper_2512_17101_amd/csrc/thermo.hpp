@@ -12,6 +12,8 @@ constexpr int kMaxSpecies = 8;
 constexpr int kMaxReactions = 8;
 constexpr double kRu = 8.314462618;  // J / (mol K)
 constexpr double kTmin = 100.0, kTmax = 6000.0;
+constexpr double kTdefault = 1000.0;  // plain (cold) Newton start
+constexpr int kLearnedMaxIter = 8;     // steps from the learned guess before the plain restart
 
 struct ThermoTable {
   int ns;

@@ -99,39 +99,36 @@ extern "C" dg_status dg_mech_destroy(dg_mech m) {
   return DG_OK;
 }
 
-extern "C" dg_status dg_temperature(dg_thermo th, int64_t n, const double* q, const double* T_guess,
-                                    double T_default, double* T_out, int32_t* iters, double tol, int max_iter,
+extern "C" dg_status dg_temperature(int64_t n, const double* q, const double* T_guess, double* T_out,
+                                    int32_t* iters, dg_thermo th, double tol, int max_iter, const dg_mlp_s* guess,
                                     hipStream_t stream) {
   if (!th) return fail(DG_ERR_ARG, "dg_temperature: null thermo");
   if (n < 0) return fail(DG_ERR_ARG, "dg_temperature: negative size");
+  if (guess) {
+    if (T_guess) return fail(DG_ERR_ARG, "dg_temperature: T_guess must be NULL when a learned guess is given");
+    return dg_temperature_learned(th, const_cast<dg_mlp>(guess), n, q, kTdefault, T_out, iters, tol, max_iter,
+                                  kLearnedMaxIter, nullptr, stream);
+  }
   if (n == 0) return DG_OK;
   if (!q || !T_out || !iters || !aligned8(q) || !aligned8(T_out) || !aligned4(iters) ||
       (T_guess && !aligned8(T_guess)))
     return fail(DG_ERR_ARG, "dg_temperature: null or misaligned pointer");
   if (!(tol > 0.0) || max_iter < 1) return fail(DG_ERR_ARG, "dg_temperature: tol must be > 0 and max_iter >= 1");
-  if (!T_guess && !(T_default >= kTmin && T_default <= kTmax))
-    return fail(DG_ERR_ARG, "dg_temperature: T_default must lie in [100, 6000] K");
-  int prev = 0;
-  hipGetDevice(&prev);
-  if (hipSetDevice(th->device) != hipSuccess) return fail(DG_ERR_HIP, "dg_temperature: hipSetDevice failed");
-  dg_status st = launch_temperature(th->t, n, q, T_guess, T_default, T_out, iters, tol, max_iter, stream);
-  hipSetDevice(prev);
-  return st;
+  DeviceGuard g(th->device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_temperature: hipSetDevice failed");
+  return launch_temperature(th->t, n, q, T_guess, kTdefault, T_out, iters, tol, max_iter, stream);
 }
 
-extern "C" dg_status dg_sources(dg_mech mech, int64_t n, const double* q, const double* T, double* omega,
+extern "C" dg_status dg_sources(int64_t n, const double* q, const double* T, double* omega, dg_mech mech,
                                 hipStream_t stream) {
   if (!mech) return fail(DG_ERR_ARG, "dg_sources: null mechanism");
   if (n < 0) return fail(DG_ERR_ARG, "dg_sources: negative size");
   if (n == 0) return DG_OK;
   if (!q || !T || !omega || !aligned8(q) || !aligned8(T) || !aligned8(omega))
     return fail(DG_ERR_ARG, "dg_sources: null or misaligned pointer");
-  int prev = 0;
-  hipGetDevice(&prev);
-  if (hipSetDevice(mech->device) != hipSuccess) return fail(DG_ERR_HIP, "dg_sources: hipSetDevice failed");
-  dg_status st = launch_sources(mech->m, n, q, T, omega, stream);
-  hipSetDevice(prev);
-  return st;
+  DeviceGuard g(mech->device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_sources: hipSetDevice failed");
+  return launch_sources(mech->m, n, q, T, omega, stream);
 }
 
 namespace dg {

@@ -29,7 +29,7 @@ EXPORTS = ("dg_reference_operators", "dg_mesh_create", "dg_mesh_info", "dg_mesh_
            "dg_temperature_learned", "dg_batch_create", "dg_batch_destroy", "dg_batch_bind",
            "dg_batch_set_config", "dg_batch_get_config", "dg_batch_rk_step", "dg_batch_info", "dg_batch_autotune",
            "dg_ns_rhs", "dg_ns_rk_step", "dg_mesh_set_launch", "dg_mesh_get_launch", "dg_autotune",
-           "dg_last_error")
+           "dg_synchronize", "dg_last_error")
 
 
 class DGError(RuntimeError):
@@ -49,7 +49,8 @@ class LaunchConfig(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
                 ("Pr", ctypes.c_double), ("Sc", ctypes.c_double), ("thermo", ctypes.c_void_p),
-                ("mech", ctypes.c_void_p)]
+                ("mech", ctypes.c_void_p), ("work", ctypes.c_void_p), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int)]
 
 
 class BatchConfig(ctypes.Structure):
@@ -88,8 +89,9 @@ def lib():
         L.dg_thermo_destroy.argtypes = [_c_p]
         L.dg_mech_create.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, _c_p, ctypes.POINTER(_c_p)]
         L.dg_mech_destroy.argtypes = [_c_p]
-        L.dg_temperature.argtypes = [_c_p, _i64, _c_p, _c_p, _dbl, _c_p, _c_p, _dbl, ctypes.c_int, _c_p]
-        L.dg_sources.argtypes = [_c_p, _i64, _c_p, _c_p, _c_p, _c_p]
+        L.dg_temperature.argtypes = [_i64, _c_p, _c_p, _c_p, _c_p, _c_p, _dbl, ctypes.c_int, _c_p, _c_p]
+        L.dg_sources.argtypes = [_i64, _c_p, _c_p, _c_p, _c_p, _c_p]
+        L.dg_synchronize.argtypes = [ctypes.c_int, _c_p]
         L.dg_mlp_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_c_p)]
         L.dg_mlp_destroy.argtypes = [_c_p]
         L.dg_mlp_set_params.argtypes = [_c_p, _c_p]
@@ -228,16 +230,60 @@ class Mesh:
 
 
 def _params(gamma: float, model: int = 0):
-    return _Params(model, gamma, 0.0, 0.0, 0.0, None, None)
+    return _Params(model, gamma, 0.0, 0.0, 0.0, None, None, None, 0.0, 0)
 
 
 MU, PR, SC = 1.8e-5, 0.71, 0.71
 NS_WORK_PER_NODE = 58  # doubles of dg_ns_rk_step scratch per node
+NS_RHS_WORK = 35       # doubles per node of dg_rhs scratch with model 1 (DG_NS_RHS_WORK)
+NS_STEP_WORK = 59      # doubles per node of dg_rk_step scratch with model 1 (DG_NS_STEP_WORK)
 
 
-def _ns_params(thermo, mech, mu, Pr, Sc):
+def _ns_params(thermo, mech, mu, Pr, Sc, work=None, tol=0.0, max_iter=0):
     return _Params(1, 0.0, float(mu), float(Pr), float(Sc), thermo.handle.value,
-                   None if mech is None else mech.handle.value)
+                   None if mech is None else mech.handle.value, None if work is None else _dev_ptr(work).value,
+                   float(tol), int(max_iter))
+
+
+def synchronize(device: int = 0, stream=None):
+    """Wait for the stream and raise DGError (DG_ERR_NONFINITE / DG_ERR_NOCONV)
+    if a kernel on the device flagged a failure since the last call."""
+    _check(lib().dg_synchronize(int(device), _stream(stream)))
+
+
+def _check_state(mesh: "Mesh", t, nf: int, name: str):
+    """A device tensor of exactly nf * E * Np doubles on the mesh's device
+    (the kernels index the state by the mesh's sizes)."""
+    if t.numel() != nf * mesh.E * mesh.Np:
+        raise ValueError(f"{name} must hold {nf} x E x Np = {nf * mesh.E * mesh.Np} doubles, got {t.numel()}")
+    if t.is_cuda and t.device.index != mesh.device:
+        raise ValueError(f"{name} lives on device {t.device.index}, the mesh on {mesh.device}")
+
+
+def reacting_rhs(mesh: "Mesh", thermo, q, out, work, mech=None, mu: float = MU, Pr: float = PR, Sc: float = SC,
+                 tol: float = 1e-10, max_iter: int = 50, stream=None):
+    """dg_rhs with model 1: reacting NS right-hand side of q [12, E, Np] into
+    out, the temperatures (from 1000 K) and gradients in work (>= 35 E Np)."""
+    _check_state(mesh, q, 12, "q")
+    _check_state(mesh, out, 12, "out")
+    if work.numel() < NS_RHS_WORK * mesh.E * mesh.Np:
+        raise ValueError("work must hold >= 35 E Np doubles")
+    prm = _ns_params(thermo, mech, mu, Pr, Sc, work, tol, max_iter)
+    _check(lib().dg_rhs(mesh.handle, ctypes.byref(prm), DG_FP64, _dev_ptr(q), _dev_ptr(out), _stream(stream)))
+    return out
+
+
+def reacting_rk_step(mesh: "Mesh", thermo, q, work, dt: float, mech=None, mu: float = MU, Pr: float = PR,
+                     Sc: float = SC, tol: float = 1e-10, max_iter: int = 50, stream=None):
+    """dg_rk_step with model 1: one LSRK(5,4) step of q [12, E, Np] in place;
+    work (>= 59 E Np doubles) holds the temperatures and stage scratch."""
+    _check_state(mesh, q, 12, "q")
+    if work.numel() < NS_STEP_WORK * mesh.E * mesh.Np:
+        raise ValueError("work must hold >= 59 E Np doubles")
+    prm = _ns_params(thermo, mech, mu, Pr, Sc, work, tol, max_iter)
+    _check(lib().dg_rk_step(mesh.handle, ctypes.byref(prm), DG_FP64, _dev_ptr(q), ctypes.c_void_p(), 0.0, float(dt),
+                            _stream(stream)))
+    return q
 
 
 def ns_rhs(mesh: Mesh, thermo, q, T, sigma, out, mech=None, mu: float = MU, Pr: float = PR, Sc: float = SC,
@@ -268,6 +314,8 @@ def ns_rk_step(mesh: Mesh, thermo, q, T, work, dt: float, mech=None, mu: float =
 
 def rhs(mesh: Mesh, q, out, precision: str = "fp64", gamma: float = 1.4, stream=None):
     """out <- DG Euler RHS of q (both [5, E, Np] float64 device tensors)."""
+    _check_state(mesh, q, 5, "q")
+    _check_state(mesh, out, 5, "out")
     prm = _params(gamma)
     _check(lib().dg_rhs(mesh.handle, ctypes.byref(prm), PRECISIONS[precision], _dev_ptr(q), _dev_ptr(out),
                         _stream(stream)))
@@ -276,8 +324,11 @@ def rhs(mesh: Mesh, q, out, precision: str = "fp64", gamma: float = 1.4, stream=
 
 def rk_step(mesh: Mesh, q, work, t: float, dt: float, precision: str = "fp64", gamma: float = 1.4, stream=None):
     """One LSRK(5,4) step, q updated in place; work holds >= 2 state arrays."""
+    _check_state(mesh, q, 5, "q")
     if work.numel() < 2 * q.numel():
         raise ValueError("work must hold at least two state arrays")
+    if work.is_cuda and work.device.index != mesh.device:
+        raise ValueError("work lives on another device than the mesh")
     prm = _params(gamma)
     _check(lib().dg_rk_step(mesh.handle, ctypes.byref(prm), PRECISIONS[precision], _dev_ptr(q), _dev_ptr(work),
                             float(t), float(dt), _stream(stream)))
@@ -351,16 +402,21 @@ class Mechanism:
             pass
 
 
-def temperature(thermo: Thermo, q, T_out, iters, T_guess=None, T_default: float = 1000.0, tol: float = 1e-10,
-                max_iter: int = 50, stream=None):
+def temperature(thermo: Thermo, q, T_out, iters, T_guess=None, tol: float = 1e-10, max_iter: int = 50,
+                guess=None, stream=None):
     """Newton temperature of the reacting state q ([5+ns, ...] float64 device
-    tensor); T_out float64 and iters int32 device tensors of q[0]'s size."""
+    tensor); T_out float64 and iters int32 device tensors of q[0]'s size.
+    Starts from T_guess, or from 1000 K, or (guess = an MLP) from the
+    network's prediction with the plain restart as fallback."""
     n = q[0].numel()
     if q.shape[0] != 5 + thermo.ns or T_out.numel() != n or iters.numel() != n:
         raise ValueError("q must be [5+ns, ...]; T_out and iters sized like one field")
+    if T_guess is not None and T_guess.numel() != n:
+        raise ValueError("T_guess must be sized like one field")
     g = _dev_ptr(T_guess) if T_guess is not None else ctypes.c_void_p()
-    _check(lib().dg_temperature(thermo.handle, n, _dev_ptr(q), g, float(T_default), _dev_ptr(T_out),
-                                _dev_ptr(iters, "int32"), float(tol), int(max_iter), _stream(stream)))
+    h = ctypes.c_void_p() if guess is None else guess.handle
+    _check(lib().dg_temperature(n, _dev_ptr(q), g, _dev_ptr(T_out), _dev_ptr(iters, "int32"), thermo.handle,
+                                float(tol), int(max_iter), h, _stream(stream)))
 
 
 def sources(mech: Mechanism, q, T, omega, stream=None):
@@ -368,7 +424,7 @@ def sources(mech: Mechanism, q, T, omega, stream=None):
     n = q[0].numel()
     if q.shape[0] != 5 + mech.ns or T.numel() != n or omega.numel() != mech.ns * n:
         raise ValueError("q [5+ns, ...], T [...], omega [ns, ...]")
-    _check(lib().dg_sources(mech.handle, n, _dev_ptr(q), _dev_ptr(T), _dev_ptr(omega), _stream(stream)))
+    _check(lib().dg_sources(n, _dev_ptr(q), _dev_ptr(T), _dev_ptr(omega), mech.handle, _stream(stream)))
 
 
 N_MLP_PARAMS = 9025

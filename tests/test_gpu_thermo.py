@@ -42,7 +42,7 @@ def test_temperature_matches_oracle():
     q = torch.from_numpy(q_np).to(dev)
     T = torch.empty(q.shape[1:], dtype=torch.float64, device=dev)
     it = torch.empty(q.shape[1:], dtype=torch.int32, device=dev)
-    dg.temperature(th, q, T, it, T_default=1000.0)
+    dg.temperature(th, q, T, it)
     torch.cuda.synchronize()
     T, it = T.cpu().numpy(), it.cpu().numpy()
     print("max |T - T_oracle| =", np.abs(T - T_ref).max(), "iteration histogram", np.bincount(it.ravel() + 1))
@@ -64,7 +64,7 @@ def test_temperature_with_guess_array_and_forced_failure():
     dg.temperature(th, q, T, it, T_guess=guess)
     torch.cuda.synchronize()
     assert np.abs(T.cpu().numpy() - T_ref).max() <= 1e-9
-    dg.temperature(th, q, T, it, T_default=1000.0, max_iter=1)
+    dg.temperature(th, q, T, it, max_iter=1)
     torch.cuda.synchronize()
     assert torch.all(it == -1)
 
@@ -122,7 +122,7 @@ def test_temperature_and_sources_full_size_sampled():
     T = torch.empty(n, dtype=torch.float64, device=dev)
     it = torch.empty(n, dtype=torch.int32, device=dev)
     om_ = torch.empty((7, n), dtype=torch.float64, device=dev)
-    dg.temperature(th, q, T, it, T_default=1000.0)
+    dg.temperature(th, q, T, it)
     dg.sources(mk, q, torch.from_numpy(T_in).to(dev), om_)
     torch.cuda.synchronize()
     idx = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(14).choice(n, 20000, replace=False)]))
