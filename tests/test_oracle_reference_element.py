@@ -1,6 +1,13 @@
 """Pins of the oracle's reference element against closed forms and exact
 integrals (nodes: warp & blend reduces to LGL edge points and face centroids
-for p <= 3; operators: exactness on polynomials, Dirichlet integrals)."""
+for p <= 3; operators: exactness on polynomials, Dirichlet integrals).
+
+The operators are exact at the FP64 nodes and rounded once, so the pins hold
+to a few units in the last place of the sums they form (Higham's bound for a
+computed dot product, (n + 2) u sum |a_j b_j|), not to a fixed 1e-12.  The
+p = 4 face-interior node positions depend on the blend parameter 0.1002,
+taken from the published table as recalled: parity unpinned for them (the
+pins below fix the LGL edge points, the centroid and the symmetry only)."""
 import itertools
 import math
 
@@ -36,7 +43,9 @@ def _closed_form_nodes(p):
 
 @pytest.mark.parametrize("p", [1, 2, 3])
 def test_nodes_closed_form(p):
-    np.testing.assert_allclose(re.nodes(p), _closed_form_nodes(p), atol=1e-14)
+    """The nodes are the correctly rounded closed forms (one unit in the
+    last place allowed where FP64 evaluates the closed form itself)."""
+    np.testing.assert_allclose(re.nodes(p), _closed_form_nodes(p), rtol=0, atol=2 * U)
 
 
 def test_nodes_p3_edge_parameter():
@@ -74,19 +83,42 @@ def _monomials(p):
     return [(a, b, c) for a in range(p + 1) for b in range(p + 1 - a) for c in range(p + 1 - a - b)]
 
 
+U = 2.0 ** -53
+
+
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_differentiation_exact_on_polynomials(p):
+    """Nodal differentiation reproduces the derivative of every monomial of
+    degree <= p at the nodes, to the rounding of the entries and the
+    products: |D u - u'| <= (Np + 8) u (|D| |u| + |u'|) per node (the dot
+    product's n u, the entries' and the monomials' own rounding)."""
     ops = re.operators(p)
     r, s, t = ops["rst"].T
+    K = ops["Np"] + 8
     for (a, b, c) in _monomials(p):
         u = r ** a * s ** b * t ** c
         dr = a * r ** max(a - 1, 0) * s ** b * t ** c
         ds = b * r ** a * s ** max(b - 1, 0) * t ** c
         dt = c * r ** a * s ** b * t ** max(c - 1, 0)
         for D, ex in ((ops["Dr"], dr), (ops["Ds"], ds), (ops["Dt"], dt)):
-            np.testing.assert_allclose(D @ u, ex, atol=2e-12 * max(1.0, np.abs(ex).max()))
+            bound = K * U * (np.abs(D) @ np.abs(u) + np.abs(ex))
+            assert np.all(np.abs(D @ u - ex) <= bound), (p, a, b, c)
     for D in (ops["Dr"], ops["Ds"], ops["Dt"]):
-        assert np.abs(D.sum(axis=1)).max() < 1e-12
+        assert np.all(np.abs(D.sum(axis=1)) <= ops["Np"] * U * np.abs(D).sum(axis=1))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_exact_operators_match_quadrature_route(p):
+    """An independent FP64 route (Legendre tensor basis, collapsed Gauss
+    quadrature) gives the same operators within its own conditioning:
+    5000 u of each row's largest entry (of the whole matrix for E, whose
+    rows of interior nodes are zero); it reaches ~2500 u at p = 4, while a
+    wrong face parametrisation, area or index order is off by O(1)."""
+    ex, fq = re.operators(p), re.operators_by_quadrature(p)
+    assert np.array_equal(ex["rst"], fq["rst"]) and np.array_equal(ex["Fmask"], fq["Fmask"])
+    for k in ("Dr", "Ds", "Dt", "M", "E", "LIFT"):
+        rm = np.abs(ex[k]).max() if k == "E" else np.abs(ex[k]).max(axis=1, keepdims=True)
+        assert np.all(np.abs(ex[k] - fq[k]) <= 5000 * U * rm), k
 
 
 def _dirichlet(exps, dim_measure, dim):
@@ -99,9 +131,9 @@ def _dirichlet(exps, dim_measure, dim):
 def test_mass_matrix_exact_integrals(p):
     ops = re.operators(p)
     M = ops["M"]
-    assert np.allclose(M, M.T, atol=1e-15)
+    assert np.array_equal(M, M.T)
     assert np.linalg.eigvalsh(M).min() > 0
-    assert abs(M.sum() - 4 / 3) < 1e-14
+    assert abs(M.sum() - 4 / 3) <= ops["Np"] ** 2 * U * np.abs(M).sum()
     lam = _bary(ops["rst"])
     rng = np.random.default_rng(0)
     for _ in range(6):
@@ -136,7 +168,9 @@ def test_face_matrix_exact_integrals(p):
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_lift_definition(p):
     ops = re.operators(p)
-    np.testing.assert_allclose(ops["M"] @ ops["LIFT"], ops["E"], atol=1e-13)
+    Np = ops["Np"]
+    bound = (Np + 2) * U * (np.abs(ops["M"]) @ np.abs(ops["LIFT"]) + np.abs(ops["E"]))
+    assert np.all(np.abs(ops["M"] @ ops["LIFT"] - ops["E"]) <= bound)
 
 
 def test_fmask_p3():
