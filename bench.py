@@ -41,8 +41,22 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "rhs_euler_fp64_p3_48cubed_pmc.txt"
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2512_17101_amd", "csrc", f) for f in ("rhs_euler.hip", "euler_point.hpp")]
 
 
+# Algorithmic work per element of one Euler RHS evaluation, by order: flops
+# (volume contraction + metric + pointwise flux + surface flux + lift) and
+# the minimum HBM bytes (FP64 state in and rhs out, 200 B of affine geometry,
+# 32 B of face connectivity).  These are the figures the roofline fraction is
+# quoted against; the kernel's own count (below) is lower because it stores
+# 72 B of geometry and folds the metric into the flux.
+ALGORITHMIC = {1: (2640, 552), 2: (9000, 1032), 3: (26400, 1832), 4: (67950, 3032)}
+
+
 def algorithmic_counts(p: int):
-    """Per-element FP64 flops and HBM bytes the RHS must move at minimum.
+    """(flops, bytes) per element of one Euler RHS (the table above)."""
+    return ALGORITHMIC[p]
+
+
+def kernel_counts(p: int):
+    """Per-element FP64 flops and HBM bytes of this library's RHS kernel.
 
     flops: contractions 2 nf Np (3 Np + 4 Nfp) + pointwise flux 52 Np + face
     flux 80 (4 Nfp).  bytes: state in and rhs out (2 nf Np 8), 9 metric terms
@@ -61,26 +75,53 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def stored_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def stored_counters():
+    """Figures per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source: HBM traffic in bytes
+    (traffic_bytes_per_launch) and the matrix-core busy fraction
+    (mfma_busy_frac).  Empty if the sources changed since."""
     if not os.path.exists(PMC_SUMMARY):
-        return None
+        return {}
     kv = {}
     for line in open(PMC_SUMMARY):
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = kernel_source_sha()
-    if kv.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in kv:
-        return None
-    return float(kv["traffic_bytes_per_launch"])
+    if kv.get("kernel_source_sha256") != kernel_source_sha():
+        return {}
+    out = {}
+    if "traffic_bytes_per_launch" in kv:
+        out["traffic"] = float(kv["traffic_bytes_per_launch"])
+    if "mfma_busy_frac" in kv:
+        out["mfma_busy"] = float(kv["mfma_busy_frac"])
+    return out
 
 
-def cpu_baseline(xyz, vid, q_np, p, sample_elems):
-    """Oracle RHS timed on a contiguous sample of elements (BLAS limited to one
-    thread, so one core does the work).  q_np maps node coordinates [E, Np, 3]
-    to the state.  Returns (record, element ids, oracle RHS on them)."""
+def stored_traffic():
+    """HBM bytes per launch from the committed counter summary, or None."""
+    return stored_counters().get("traffic")
+
+
+def cpu_model():
+    """Model name of the host CPU (from /proc/cpuinfo) and the cores this
+    process may run on."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(xyz, vid, q_np, p, sample_elems, threads):
+    """Oracle RHS timed on a contiguous sample of elements, once with BLAS on
+    one thread and once on `threads` threads (the NumPy oracle's contractions
+    are BLAS calls; its pointwise work runs on one core either way).  q_np
+    maps node coordinates [E, Np, 3] to the state.  Returns (record, element
+    ids, oracle RHS on them, oracle term magnitudes on them)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import euler as oe, mesh as om, reference_element as ore
@@ -91,16 +132,72 @@ def cpu_baseline(xyz, vid, q_np, p, sample_elems):
     # the oracle's own nodes: the same smooth state evaluated there (it agrees
     # with the library's nodes to rounding), so no oracle input comes from the library
     q_np = q_np(om.node_coordinates(xyz, ops["rst"]))
-    with threadpool_limits(limits=1):
-        oe.rhs(ops, geo, conn, q_np, elems=idx[:1024])
-        t0 = time.perf_counter()
-        ref = oe.rhs(ops, geo, conn, q_np, elems=idx)
-        t = time.perf_counter() - t0
+    times = {}
+    for nt in (1, threads):
+        with threadpool_limits(limits=nt):
+            oe.rhs(ops, geo, conn, q_np, elems=idx[:1024])
+            t0 = time.perf_counter()
+            ref = oe.rhs(ops, geo, conn, q_np, elems=idx)
+            times[nt] = time.perf_counter() - t0
+    with threadpool_limits(limits=threads):
+        mag = oe.rhs_term_magnitude(ops, geo, conn, q_np, elems=idx)
     Np = ops["Np"]
-    rec = {"value": len(idx) * Np * NF / t / 1e9, "unit": "GDOF·fields/s", "cores": 1, "kind": "oracle",
+    model, ncpu = cpu_model()
+    rate = lambda t: len(idx) * Np * NF / t / 1e9
+    best = min(times, key=times.get)
+    rec = {"value": rate(times[best]), "unit": "GDOF·fields/s", "cores": best, "kind": "oracle",
            "sample": f"one RHS over elements 0..{len(idx) - 1} of the {xyz.shape[0]}-tet mesh "
-                     f"({t:.1f} s, NumPy FP64, 1 thread)"}
-    return rec, idx, ref
+                     f"({times[best]:.1f} s, NumPy FP64, BLAS on {best} threads)",
+           "cpu_model": model, "cpus_available": ncpu,
+           "by_threads": {str(nt): {"seconds": round(t, 2), "value": rate(t)} for nt, t in times.items()}}
+    return rec, idx, ref, mag
+
+
+FIELDS = ("rho", "rho_u", "rho_v", "rho_w", "E")
+
+
+def entry_ratios(got, ref, mag, p):
+    """Per field: the largest |gpu_i - oracle_i| / T_i over the sample, in
+    units of u = 2^-53, with T_i the oracle's term magnitude of entry i (the
+    scale of the rounding of a computed sum of products), the per-entry bar
+    K = 3 Np + 4 Nfp it is held to in the tests, and max|rhs_f| / max T_f
+    (how far the field's terms cancel)."""
+    u = 2.0 ** -53
+    Np = (p + 1) * (p + 2) * (p + 3) // 6
+    Nfp = (p + 1) * (p + 2) // 2
+    K = 3 * Np + 4 * Nfp
+    r = (np.abs(got - ref) / mag).max(axis=(1, 2)) / u
+    c = np.abs(ref).max(axis=(1, 2)) / mag.max(axis=(1, 2))
+    return {nm: {"max_err_over_T_in_u": round(float(r[f]), 3), "bar_in_u": K, "max_rhs_over_max_T": float(c[f])}
+            for f, nm in enumerate(FIELDS)}
+
+
+def long_run_errors(dg, mesh, q, q_np, work, modes, steps, stream):
+    """Per-field errors of the reduced-precision forms against the FP64 form
+    after `steps` LSRK steps from the same state, CFL 0.2 on the cube size
+    (dt = 0.2 h / ((p + 1)^2 max(|u| + c)) from the initial state)."""
+    import torch
+    rho = q_np[0]
+    vel = np.sqrt(q_np[1] ** 2 + q_np[2] ** 2 + q_np[3] ** 2) / rho
+    pres = (1.4 - 1.0) * (q_np[4] - 0.5 * rho * vel ** 2)
+    vmax = float((vel + np.sqrt(1.4 * pres / rho)).max())
+    h = 10.0 / round((mesh.E / 6) ** (1.0 / 3.0))
+    dt = 0.2 * h / ((mesh.order + 1) ** 2 * vmax)
+    finals = {}
+    with torch.cuda.stream(stream):
+        for mode in modes:
+            qs = q.clone()
+            for _ in range(steps):
+                dg.rk_step(mesh, qs, work, 0.0, dt, mode, stream=stream)
+            stream.synchronize()
+            finals[mode] = qs.cpu().numpy()
+    ref = finals["fp64"]
+    out = {"steps": steps, "dt": dt, "t_final": steps * dt, "reference": "GPU FP64 form"}
+    for mode in modes:
+        if mode != "fp64":
+            out[mode] = field_errors(finals[mode], ref)
+    out["fp64_finite"] = bool(np.isfinite(ref).all())
+    return out
 
 
 def field_errors(got, ref):
@@ -113,25 +210,32 @@ def field_errors(got, ref):
     ni = np.abs(ref).max(axis=(1, 2))
     n2[1:4] = n2[1:4].max()
     ni[1:4] = ni[1:4].max()
-    names = ("rho", "rho_u", "rho_v", "rho_w", "E")
-    return {nm: {"l2": float(l2[f] / n2[f]), "linf": float(li[f] / ni[f])} for f, nm in enumerate(names)}
+    return {nm: {"l2": float(l2[f] / n2[f]), "linf": float(li[f] / ni[f])} for f, nm in enumerate(FIELDS)}
+
+
+SETTLE_S = 0.5  # seconds of untimed launches before the first timed batch (clocks ramp up)
+REPEATS = 5    # batches of `steps` launches timed after the reported one, for the spread
 
 
 def time_rhs(dg, mesh, q, out, precision, steps, warmup, stream):
-    """Average duration of one dg_rhs launch, HIP events on its stream."""
+    """Average duration of one dg_rhs launch, HIP events on its stream: a
+    settle phase of SETTLE_S seconds of launches, `warmup` launches, then one
+    timed batch of exactly `steps` launches (the reported figure), then
+    REPEATS more batches of the same size for the spread."""
     import torch
+    launch = lambda: dg.rhs(mesh, q, out, precision, stream=stream)
     with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < SETTLE_S:
+            for _ in range(50):
+                launch()
+            stream.synchronize()
         for _ in range(warmup):
-            dg.rhs(mesh, q, out, precision, stream=stream)
+            launch()
         stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            dg.rhs(mesh, q, out, precision, stream=stream)
-        e1.record(stream)
-        stream.synchronize()
-    return e0.elapsed_time(e1) / steps
+        batches = [_time_ms(stream, launch, steps) for _ in range(1 + REPEATS)]
+    return batches[0], {"median": round(float(np.median(batches)), 5), "min": round(min(batches), 5),
+                        "max": round(max(batches), 5), "batches": len(batches), "launches_per_batch": steps}
 
 
 def time_rk_step(dg, mesh, q, work, dt, precision, steps, stream):
@@ -304,47 +408,99 @@ def reacting_leg(dg, wl, dev, stream, steps):
            "unit": "GDOF·fields/s (gradient + right-hand side, sources included)",
            "temperature_ms": round(ms_T, 4), "sources_ms": round(ms_src, 4),
            "newton_mean_iters_from_1000K": round(float(iters.mean()), 3),
+           "newton_iters_histogram": iteration_histogram(iters),
            "newton_failures": int((iters < 0).sum()), "rk_step_ms": round(ms_rk, 4), "rk_dt": dt_rk,
            "finite": finite}
     return rec
 
 
+LEARNED_DT = 2e-9     # s: LSRK step of the snapshot run (acoustic CFL about 0.1 on the 32^3 p = 3 mesh)
+LEARNED_STEPS = 100   # steps of the snapshot run
+LEARNED_EVERY = 10    # a snapshot every this many steps (steps 0, 10, ..., 100)
+LEARNED_STATES = 2_000_000
+LEARNED_HELD_OUT = 0.1
+LEARNED_EPOCHS = 20
+LEARNED_BATCH = 4096
+
+
 def learned_leg(dg, wl, dev, stream, X48):
     """Learned temperature guess: the 9-64-64-64-1 network trained on the GPU
-    (BF16 matrix cores, FP32 masters, Adam) on 2M node states of reacting
-    fields on the 32^3 p=3 mesh (other seeds), then evaluated inside Newton on
-    the 48^3 p=3 mesh's 13.27M nodes carrying reacting fields (coordinates
-    scaled to the 1 cm box).  Plain Newton from 1000 K is the reference."""
+    (BF16 matrix cores, FP32 masters, Adam, lr 1e-3) on states the reacting
+    solver produces: the 32^3 p = 3 reacting run (seeded fronts, sources off,
+    LSRK steps of LEARNED_DT) snapshotted every LEARNED_EVERY steps, targets
+    from plain-guess Newton; 2M states sampled without replacement (seed
+    4001), 10 % held out; init seed 4002, shuffle seed 4003.  Then evaluated
+    inside Newton on the 48^3 p = 3 mesh's 13.27M nodes carrying reacting
+    fields (coordinates scaled to the 1 cm box).  Plain Newton from 1000 K is
+    the reference."""
     import torch
     TH = wl.synthetic_thermo(3003)
     th = dg.Thermo(TH["W"], TH["a"])
-    # training states
-    xyz, vid = wl.kuhn_box_mesh(32, 0.01, 0.03, 1003)
-    m32 = dg.Mesh(3, xyz, vid, 0)
-    X32 = m32.nodes().reshape(-1, 3)
-    qs = [torch.from_numpy(wl.reacting_state(X32, seed=sd, L=0.01, n_cells=32)).to(dev) for sd in (3105, 3205)]
-    qtr = torch.cat(qs, dim=1).contiguous()
-    del qs
+    n32, p = 32, 3
+    xyz, vid = wl.kuhn_box_mesh(n32, 0.01, 0.03, 1003)
+    m32 = dg.Mesh(p, xyz, vid, 0)
+    nn = m32.E * m32.Np
+    q = torch.from_numpy(wl.reacting_state(m32.nodes().reshape(-1, 3), seed=3005, L=0.01, n_cells=n32)
+                         .reshape(12, m32.E, m32.Np)).to(dev)
+    T = torch.empty((m32.E, m32.Np), dtype=torch.float64, device=dev)
+    it = torch.empty((m32.E, m32.Np), dtype=torch.int32, device=dev)
+    work = torch.empty(dg.NS_WORK_PER_NODE * nn, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        dg.temperature(th, q, T, it, stream=stream)
+        snaps = [q.reshape(12, nn).clone()]
+        for step in range(1, LEARNED_STEPS + 1):
+            dg.ns_rk_step(m32, th, q, T, work, LEARNED_DT, mech=None, stream=stream)
+            if step % LEARNED_EVERY == 0:
+                snaps.append(q.reshape(12, nn).clone())
+        dg.synchronize(0, stream)
+    run_s = time.perf_counter() - t0
+    del work, T, it
+    qtr = torch.cat(snaps, dim=1).contiguous()
+    del snaps
     ntr = qtr.shape[1]
     Ttr = torch.empty(ntr, dtype=torch.float64, device=dev)
     itr = torch.empty(ntr, dtype=torch.int32, device=dev)
     dg.temperature(th, qtr, Ttr, itr)
-    gen = torch.Generator().manual_seed(4003)
-    pick = torch.randperm(ntr, generator=gen)[:2_000_000].to(dev)
+    pick = torch.randperm(ntr, generator=torch.Generator().manual_seed(4001))[:LEARNED_STATES].to(dev)
+    n_val = int(LEARNED_HELD_OUT * LEARNED_STATES)
+    val, train = pick[:n_val].contiguous(), pick[n_val:].contiguous()
     net = dg.MLP(seed=4002)
-    net.fit_normalization(qtr, pick, Ttr)
+    net.fit_normalization(qtr, train, Ttr)
+    gen = torch.Generator().manual_seed(4003)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    batch, epochs = 4096, 4
-    nb = pick.numel() // batch
+    batch = LEARNED_BATCH
+    nb = train.numel() // batch
+
+    def held_out_loss():
+        acc, cnt = 0.0, 0
+        for b in range(0, val.numel(), batch):
+            sl = val[b:b + batch]
+            net.loss_grad(qtr, sl, Ttr, loss=loss, stream=stream)
+            stream.synchronize()
+            acc += loss.item() * sl.numel()
+            cnt += sl.numel()
+        return acc / cnt
+
     t0 = time.perf_counter()
+    epoch_loss = []
     with torch.cuda.stream(stream):
-        for ep in range(epochs):
-            perm = pick[torch.randperm(pick.numel(), generator=gen).to(dev)]
+        for ep in range(LEARNED_EPOCHS):
+            perm = train[torch.randperm(train.numel(), generator=gen).to(dev)]
             for b in range(nb):
                 net.train_step(qtr, perm[b * batch:(b + 1) * batch], Ttr, lr=1e-3, loss=loss, stream=stream)
+            if ep in (0, LEARNED_EPOCHS // 2 - 1, LEARNED_EPOCHS - 1):
+                epoch_loss.append((ep + 1, loss.item()))
         stream.synchronize()
     train_s = time.perf_counter() - t0
-    del qtr, Ttr, itr, pick
+    with torch.cuda.stream(stream):
+        val_loss = held_out_loss()
+        qv = qtr.index_select(1, val).contiguous()
+        Tv_pred = torch.empty(n_val, dtype=torch.float64, device=dev)
+        net.predict(qv, Tv_pred, stream=stream)
+        stream.synchronize()
+    val_rms = float(((Tv_pred - Ttr.index_select(0, val)) ** 2).mean().sqrt().item())
+    del qtr, Ttr, itr, pick, qv
     # evaluation on the 48^3 mesh's nodes
     q = torch.from_numpy(wl.reacting_state(X48.reshape(-1, 3) * 1e-3, seed=3005, L=0.01, n_cells=48)).to(dev)
     n = q.shape[1]
@@ -365,15 +521,27 @@ def learned_leg(dg, wl, dev, stream, X48):
     torch.cuda.synchronize()
     ipn, iln = ip.cpu().numpy(), il.cpu().numpy()
     return {"workload": "reacting_fields_on_48cubed_p3_nodes", "nodes": n,
-            "train": {"states": 2_000_000, "batch": batch, "epochs": epochs, "adam_steps": epochs * nb,
-                      "final_batch_loss": round(loss.item(), 6), "seconds": round(train_s, 2)},
+            "train": {"source": f"32^3 p=3 reacting NS run (sources off), dt {LEARNED_DT:g} s, snapshots every "
+                                f"{LEARNED_EVERY} of {LEARNED_STEPS} steps", "pool_states": ntr,
+                      "states": LEARNED_STATES, "held_out": n_val, "batch": batch, "epochs": LEARNED_EPOCHS,
+                      "adam_steps": LEARNED_EPOCHS * nb, "batch_loss_by_epoch": epoch_loss,
+                      "held_out_loss": round(val_loss, 8), "held_out_rms_error_K": round(val_rms, 4),
+                      "run_seconds": round(run_s, 2), "train_seconds": round(train_s, 2),
+                      "samples_per_s": round(LEARNED_EPOCHS * nb * batch / train_s, 1)},
             "plain": {"ms": round(ms_p, 4), "mean_iters": round(float(ipn.mean()), 3),
-                      "failures": int((ipn < 0).sum())},
+                      "failures": int((ipn < 0).sum()), "iters_histogram": iteration_histogram(ipn)},
             "learned": {"ms": round(ms_l, 4), "mean_iters": round(float(iln.mean()), 3),
                         "fallbacks": fallbacks, "fallback_rate": fallbacks / n,
+                        "iters_histogram": iteration_histogram(iln),
                         "max_abs_dT_vs_plain_K": float((Tl - Tp).abs().max().item()),
                         "guess_rms_error_K": float(((Tpred - Tp) ** 2).mean().sqrt().item())},
             "speedup_vs_plain": round(ms_p / ms_l, 3)}
+
+
+def iteration_histogram(iters):
+    """{iterations: node count} of a Newton solve (-1 = failed)."""
+    vals, counts = np.unique(iters, return_counts=True)
+    return {str(int(v)): int(c) for v, c in zip(vals, counts)}
 
 
 def main():
@@ -386,6 +554,10 @@ def main():
     ap.add_argument("--no-rk", action="store_true", help="skip the LSRK step timing")
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="elements in the CPU-baseline sample (-1: the whole mesh, 0: skip)")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, len(os.sched_getaffinity(0))),
+                    help="BLAS threads of the CPU baseline's second timing (the first uses one)")
+    ap.add_argument("--long-steps", type=int, default=100,
+                    help="LSRK steps of the reduced-precision forms against the FP64 form (0: skip)")
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="cubes per side (default: the 48^3 workload)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched leg")
     ap.add_argument("--batched-only", action="store_true", help="run only the 64-mesh batched leg")
@@ -436,25 +608,28 @@ def main():
     torch.cuda.synchronize()
     E, Np = mesh.E, mesh.Np
     modes = ["fp64", "fp32", "split_bf16"] if args.precision == "all" else [args.precision]
-    outs, ms = {}, {}
+    outs, ms, spread = {}, {}, {}
     for mode in modes:
         outs[mode] = torch.empty_like(q)
-        ms[mode] = time_rhs(dg, mesh, q, outs[mode], mode, args.steps, args.warmup, stream)
+        ms[mode], spread[mode] = time_rhs(dg, mesh, q, outs[mode], mode, args.steps, args.warmup, stream)
     torch.cuda.synchronize()
     head = modes[0]
     value = E * Np * NF / (ms[head] * 1e-3) / 1e9
     flops, bytes_ = algorithmic_counts(p)
+    kflops, kbytes = kernel_counts(p)
     achieved_tf = flops * E / (ms[head] * 1e-3) / 1e12
     achieved_gbs = bytes_ * E / (ms[head] * 1e-3) / 1e9
     # the stored counters describe the FP64 kernel on the 48^3 workload only
-    traffic = stored_traffic() if head == "fp64" and args.n == WORKLOAD["n"] else None
+    on_workload = args.n == WORKLOAD["n"]
+    counters = stored_counters() if head == "fp64" and on_workload else {}
     hbm_view = {"achieved": round(achieved_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved_gbs / PEAK_HBM_GBS, 4)}
     if head == "fp64":
         roofline = {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                    "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": counters.get("traffic"),
                     "kernel": f"rhs_euler_fp64_kernel<{p}>", "flops_per_elem": flops, "bytes_per_elem": bytes_,
-                    "hbm_view": hbm_view}
+                    "kernel_flops_per_elem": kflops, "kernel_bytes_per_elem": kbytes,
+                    "mfma_busy": counters.get("mfma_busy"), "hbm_view": hbm_view}
     else:
         # reduced-precision contractions: the FP64 pipe keeps only the
         # pointwise work, and the kernel's bound is HBM
@@ -464,15 +639,15 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms[head], 5), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
            "dtype": {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3-f32acc"}[head], "data": "synthetic",
-           "config": {"workload": WORKLOAD["name"] if args.n == WORKLOAD["n"] else f"euler_vortex_pert_p3_{args.n}cubed",
+           "config": {"workload": WORKLOAD["name"] if on_workload else f"euler_vortex_pert_p3_{args.n}cubed",
                       "elements": E, "order": p, "nodes_per_element": Np, "fields": NF,
                       "contraction_precision": head},
-           "roofline": roofline}
+           "roofline": roofline, "ms_per_step_spread": spread[head]}
     variants = {}
     for mode in modes[1:]:
         gbs = bytes_ * E / (ms[mode] * 1e-3) / 1e9
         variants[mode] = {"value": round(E * Np * NF / (ms[mode] * 1e-3) / 1e9, 3), "ms_per_step": round(ms[mode], 5),
-                          "speedup_vs_fp64": round(ms[head] / ms[mode], 3),
+                          "ms_per_step_spread": spread[mode], "speedup_vs_fp64": round(ms[head] / ms[mode], 3),
                           "hbm_view": {"achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                        "frac": round(gbs / PEAK_HBM_GBS, 4)}}
     if not args.no_rk:
@@ -485,15 +660,21 @@ def main():
             t_rk = time_rk_step(dg, mesh, qs, work, 1e-4, mode, max(2, args.steps // 10), stream)
             (rec if mode == head else variants[mode])["lsrk_step_ms"] = round(t_rk, 4)
             (rec if mode == head else variants[mode])["lsrk_launch"] = cfg
+        if len(modes) > 1 and args.long_steps > 0:
+            rec["after_steps"] = long_run_errors(dg, mesh, q, q_np, work, modes, args.long_steps, stream)
         del work, qs
     if args.cpu_sample != 0:
         state = lambda Xn: wl.vortex_state(Xn, pert=wl.density_perturbation(WORKLOAD["pert_seed"]))
-        cpu, idx, ref = cpu_baseline(xyz, vid, state, p, args.cpu_sample)
+        cpu, idx, ref, mag = cpu_baseline(xyz, vid, state, p, args.cpu_sample, args.cpu_threads)
         rec["cpu_baseline"] = cpu
         idx_t = torch.from_numpy(idx).to(dev)
         for mode in modes:
             got = outs[mode].index_select(1, idx_t).cpu().numpy()
             errs = field_errors(got, ref)
+            if mode == "fp64":
+                ratio = entry_ratios(got, ref, mag, p)
+                for f, nm in enumerate(FIELDS):
+                    errs[nm].update(ratio[nm])
             if mode == head:
                 rec["error_vs_oracle"] = errs
             else:

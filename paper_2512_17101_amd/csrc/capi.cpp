@@ -28,6 +28,40 @@ const double kLsrkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 1
                           1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                           2277821191437.0 / 14882151754819.0};
 
+// One LSRK(5,4) Euler step of q in place with work = [residual | second
+// state buffer] (2 n doubles); the device is current.  Allocates nothing.
+dg_status rk_step_euler(const Mesh& m, double gamma, dg_precision prec, double* q, double* work, double dt,
+                        hipStream_t stream) {
+  const size_t n = static_cast<size_t>(5) * m.E * m.Np;
+  dg_status st = DG_OK;
+  double* res = work;
+  if (!m.launch[prec].rk_fused) {
+    // RHS into work + n, then the pointwise stage update of q in place
+    double* rhs = work + n;
+    for (int s = 0; s < 5; ++s) {
+      st = prec == DG_FP64
+               ? launch_rhs_euler_fp64(m, gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream)
+               : launch_rhs_euler_lowp(m, prec, gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+      if (st != DG_OK) return st;
+      st = launch_lsrk_update(static_cast<int64_t>(n), kLsrkA[s], kLsrkB[s], dt, rhs, res, q, stream);
+      if (st != DG_OK) return st;
+    }
+    return DG_OK;
+  }
+  double* buf[2] = {q, work + n};
+  for (int s = 0; s < 5; ++s) {
+    const double* qin = buf[s & 1];
+    double* qout = buf[(s + 1) & 1];
+    st = prec == DG_FP64
+             ? launch_rhs_euler_fp64(m, gamma, qin, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt, true, stream)
+             : launch_rhs_euler_lowp(m, prec, gamma, qin, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt, true, stream);
+    if (st != DG_OK) return st;
+  }
+  // five stages leave the state in the second buffer
+  DG_HIP(hipMemcpyAsync(q, buf[1], n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  return DG_OK;
+}
+
 }  // namespace dg
 
 using namespace dg;
@@ -107,32 +141,7 @@ extern "C" dg_status dg_rk_step(dg_mesh h, const dg_params* prm, dg_precision pr
   if (work < q + n && q < work + 2 * n) return fail(DG_ERR_ARG, "dg_rk_step: work overlaps q");
   DeviceGuard g(m.device);
   if (!g.ok) return fail(DG_ERR_HIP, "dg_rk_step: hipSetDevice failed");
-  double* res = work;
-  if (!m.launch[prec].rk_fused) {
-    // RHS into work + n, then the pointwise stage update of q in place
-    double* rhs = work + n;
-    for (int s = 0; s < 5; ++s) {
-      st = prec == DG_FP64
-               ? launch_rhs_euler_fp64(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream)
-               : launch_rhs_euler_lowp(m, prec, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
-      if (st != DG_OK) return st;
-      st = launch_lsrk_update(static_cast<int64_t>(n), kLsrkA[s], kLsrkB[s], dt, rhs, res, q, stream);
-      if (st != DG_OK) return st;
-    }
-    return DG_OK;
-  }
-  double* buf[2] = {q, work + n};
-  for (int s = 0; s < 5; ++s) {
-    const double* qin = buf[s & 1];
-    double* qout = buf[(s + 1) & 1];
-    st = prec == DG_FP64
-             ? launch_rhs_euler_fp64(m, prm->gamma, qin, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt, true, stream)
-             : launch_rhs_euler_lowp(m, prec, prm->gamma, qin, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt, true, stream);
-    if (st != DG_OK) return st;
-  }
-  // five stages leave the state in the second buffer
-  DG_HIP(hipMemcpyAsync(q, buf[1], n * sizeof(double), hipMemcpyDeviceToDevice, stream));
-  return DG_OK;
+  return dg::rk_step_euler(m, prm->gamma, prec, q, work, dt, stream);
 }
 
 extern "C" dg_status dg_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,

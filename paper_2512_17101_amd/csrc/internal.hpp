@@ -120,6 +120,10 @@ dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, 
                                 hipStream_t s);
 dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,
                              double* q, hipStream_t s);
+// One LSRK(5,4) Euler step of q in place; work = [residual | second state
+// buffer] (2 x 5 E Np doubles); the mesh's device is current.
+dg_status rk_step_euler(const Mesh& m, double gamma, dg_precision prec, double* q, double* work, double dt,
+                        hipStream_t stream);
 // dg_rhs / dg_rk_step with model 1 (reacting Navier-Stokes), prm->work scratch.
 dg_status ns_rhs_model1(const Mesh& m, const dg_params* prm, const double* q, double* rhs, hipStream_t s);
 dg_status ns_step_model1(const Mesh& m, const dg_params* prm, double* q, double dt, hipStream_t s);

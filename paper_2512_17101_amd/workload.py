@@ -170,17 +170,17 @@ WORKLOADS = {
 
 
 
-def batch_specs(n_meshes: int = 64, n_min: int = 4, n_max: int = 40, seed: int = 5005):
+def batch_specs(n_meshes: int = 64, n_min: int = 4, n_max: int = 40, seed: int = 5001, mesh_seed0: int = 5100):
     """Seeded specification of a batch of independent periodic vortex boxes
     [0, 10]^3: box size n ~ U{n_min..n_max} cubes per side (6 n^3 tets),
     order p ~ U{1..4}, vortex centre ~ U[3, 7]^2, strength beta ~ U[3, 5],
-    5 % vertex jitter, one mesh seed per entry."""
+    5 % vertex jitter; mesh i has seed mesh_seed0 + i."""
     rng = np.random.default_rng(seed)
     n = rng.integers(n_min, n_max + 1, n_meshes)
     p = rng.integers(1, 5, n_meshes)
     centre = rng.uniform(3.0, 7.0, (n_meshes, 2))
     beta = rng.uniform(3.0, 5.0, n_meshes)
-    return [dict(n=int(n[i]), order=int(p[i]), jitter=0.05, mesh_seed=seed * 100 + i,
+    return [dict(n=int(n[i]), order=int(p[i]), jitter=0.05, mesh_seed=mesh_seed0 + i,
                  center=(float(centre[i, 0]), float(centre[i, 1])), beta=float(beta[i]))
             for i in range(n_meshes)]
 

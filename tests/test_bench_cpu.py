@@ -7,6 +7,7 @@ import shutil
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 import bench
@@ -23,11 +24,37 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_counts_at_p3():
+    # the roofline's per-element figures: 12.0k volume + 1.8k metric + 0.6k
+    # flux + 4.0k surface + 8.0k lift flops; bytes: state in and rhs out
+    # (2 * 5 * 20 * 8) + 200 (affine geometry) + 32 (connectivity)
+    assert bench.algorithmic_counts(3) == (12000 + 1800 + 600 + 4000 + 8000, 2 * 5 * 20 * 8 + 200 + 32)
+    for p in (1, 2, 3, 4):
+        Np = (p + 1) * (p + 2) * (p + 3) // 6
+        assert bench.algorithmic_counts(p)[1] == 2 * 5 * Np * 8 + 232
+
+
+def test_kernel_counts_at_p3():
     # 2 nf Np (3 Np + 4 Nfp) = 2 * 5 * 20 * 100 = 20,000 contraction flops,
     # 52 * 20 pointwise and 80 * 40 face-flux flops; bytes: 2 * 5 * 20 * 8 +
     # 72 (metric) + 32 (connectivity)
-    assert bench.algorithmic_counts(3) == (20000 + 1040 + 3200, 1704)
-    assert bench.algorithmic_counts(1) == (2 * 5 * 4 * (12 + 12) + 52 * 4 + 80 * 12, 2 * 5 * 4 * 8 + 104)
+    assert bench.kernel_counts(3) == (20000 + 1040 + 3200, 1704)
+    assert bench.kernel_counts(1) == (2 * 5 * 4 * (12 + 12) + 52 * 4 + 80 * 12, 2 * 5 * 4 * 8 + 104)
+
+
+def test_iteration_histogram():
+    h = bench.iteration_histogram(np.array([3, 5, 5, -1, 3, 3]))
+    assert h == {"-1": 1, "3": 3, "5": 2}
+
+
+def test_entry_ratios_units():
+    """Errors are quoted in units of u relative to each entry's magnitude."""
+    u = 2.0 ** -53
+    ref = np.ones((5, 2, 20))
+    mag = np.full_like(ref, 4.0)
+    got = ref + 8 * u  # 8 u absolute on a magnitude of 4: 2 u
+    r = bench.entry_ratios(got, ref, mag, 3)
+    assert abs(r["rho"]["max_err_over_T_in_u"] - 2.0) < 1e-9 and r["E"]["bar_in_u"] == 100
+    assert r["rho"]["max_rhs_over_max_T"] == 0.25
 
 
 def test_stored_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):

@@ -162,14 +162,17 @@ def test_reacting_model_through_rhs_and_rk_step():
     dg.synchronize()
     assert torch.equal(out1, out2)
     assert torch.equal(work[:nn].view(mesh.E, mesh.Np), T)
-    qa, qb = q.clone(), q.clone()
-    dt = 1e-9
-    dg.reacting_rk_step(mesh, th, qa, work, dt, mech=mk)
-    Tb = torch.full((mesh.E, mesh.Np), 1000.0, dtype=torch.float64, device=dev)
-    wb = torch.empty(dg.NS_WORK_PER_NODE * nn, dtype=torch.float64, device=dev)
-    dg.ns_rk_step(mesh, th, qb, Tb, wb, dt, mech=mk)
-    dg.synchronize()
-    assert torch.equal(qa, qb)
+    # with sources the seeded rates (A up to 1e12 SI) are stiff: an explicit
+    # step of 1e-14 s; without them an acoustic-scale step of 1e-9 s
+    for mech, dt in ((mk, 1e-14), (None, 1e-9)):
+        qa, qb = q.clone(), q.clone()
+        dg.reacting_rk_step(mesh, th, qa, work, dt, mech=mech)
+        Tb = torch.full((mesh.E, mesh.Np), 1000.0, dtype=torch.float64, device=dev)
+        wb = torch.empty(dg.NS_WORK_PER_NODE * nn, dtype=torch.float64, device=dev)
+        dg.ns_rk_step(mesh, th, qb, Tb, wb, dt, mech=mech)
+        dg.synchronize()
+        assert torch.equal(qa, qb)
+        assert not torch.equal(qa, q)
     # reduced-precision contractions are not offered for the reacting model
     with pytest.raises(dg.DGError) as ei:
         prm = dg._ns_params(th, mk, dg.MU, dg.PR, dg.SC, work)
