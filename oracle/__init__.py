@@ -16,6 +16,8 @@ Modules:
   reference_element  nodes (warp & blend), Lagrange operators Dr/Ds/Dt, mass,
                      face mass, LIFT, Fmask
   mesh               affine geometry, face normals/areas, face-node connectivity
+  hex                tensor-product hexahedra: LGL nodes, 1-D operators, factored
+                     lift, Euler RHS on periodic rectilinear grids
   euler              strong-form Euler RHS with a local Lax-Friedrichs flux
   lsrk               five-stage, fourth-order low-storage Runge-Kutta
   precision          FP32 / split-BF16 contraction emulation and error bounds

@@ -17,7 +17,9 @@ stands in for by these synthetic meshes and states):
   z) on an ideal gas, optionally with a smooth periodic entropy perturbation of
   the density;
 * constant states and "entropy waves" (constant velocity and pressure,
-  arbitrary density) used by invariance tests.
+  arbitrary density) used by invariance tests;
+* periodic rectilinear boxes of hexahedra (jittered grid lines) for the
+  tensor-product elements of the paper's own benchmarks (Sec. 5.2).
 """
 from __future__ import annotations
 
@@ -76,6 +78,36 @@ def kuhn_mesh(dims, lengths, jitter: float = 0.05, seed: int = 0):
 def kuhn_box_mesh(n: int, L: float = 10.0, jitter: float = 0.05, seed: int = 0):
     """Cubic periodic box [0, L]^3 of n^3 cubes x 6 tets (see kuhn_mesh)."""
     return kuhn_mesh((n, n, n), (L, L, L), jitter, seed)
+
+
+def rectilinear_grid(dims, lengths, jitter: float = 0.05, seed: int = 0):
+    """Grid lines of a periodic rectilinear box of nx * ny * nz hexahedra.
+
+    Returns three arrays g_d of n_d + 1 strictly increasing coordinates: line
+    i of axis d sits at i h_d + U[-jitter h_d, jitter h_d] (h_d = L_d / n_d)
+    for i < n_d, and the last line is the first one shifted by the period,
+    g_d[n_d] = g_d[0] + L_d, so the box stays periodic with volume L^3 and
+    every cell is an axis-aligned box (an affine element).  Cell (i, j, k)
+    spans [g_x[i], g_x[i+1]] x [g_y[j], g_y[j+1]] x [g_z[k], g_z[k+1]]."""
+    if not 0.0 <= jitter < 0.5:
+        raise ValueError("jitter must be in [0, 0.5)")
+    rng = np.random.default_rng(seed)
+    out = []
+    for n, L in zip(dims, lengths):
+        n = int(n)
+        if n < 1:
+            raise ValueError("cell counts must be >= 1")
+        h = L / n
+        g = np.arange(n + 1) * h
+        g[:n] += rng.uniform(-jitter * h, jitter * h, n)
+        g[n] = g[0] + L
+        out.append(g)
+    return tuple(out)
+
+
+def rectilinear_box(n: int, L: float = 10.0, jitter: float = 0.05, seed: int = 0):
+    """Cubic periodic rectilinear box of n^3 hexahedra (see rectilinear_grid)."""
+    return rectilinear_grid((n, n, n), (L, L, L), jitter, seed)
 
 
 def vortex_slab_mesh(n: int, L: float = 10.0, nz: int = 3, jitter: float = 0.05, seed: int = 0):

@@ -1,0 +1,251 @@
+"""Pins of the oracle's tensor-product hexahedron (the element of the paper's
+own benchmarks, Sec. 5.2) against what the mathematics fixes: LGL points in
+closed form, exact 1-D differentiation and mass, the factored lift against
+the unfactored definition M^-1 E built from the 3-D mass and face matrices,
+free-stream preservation, discrete conservation, the entropy-wave special
+case, exact volume divergence of polynomial fluxes, the Lax-Friedrichs
+dissipation identity, and convergence to the isentropic vortex."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import euler as oe, hex as oh, lsrk
+from paper_2512_17101_amd import workload as wl
+
+U = 2.0 ** -53
+
+
+def _setup(p, dims=(3, 4, 2), jitter=0.1, seed=11, L=10.0):
+    gr = oh.grid(*wl.rectilinear_grid(dims, (L, L * dims[1] / dims[0], L * dims[2] / dims[0]), jitter, seed))
+    ops = oh.operators_1d(p)
+    X = oh.node_coordinates(gr, p)
+    return ops, gr, X
+
+
+@pytest.fixture(scope="module", params=[1, 2, 3, 4])
+def hexp(request):
+    return _setup(request.param)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_gll_points_closed_form(p):
+    ref = {1: [-1, 1], 2: [-1, 0, 1], 3: [-1, -1 / math.sqrt(5), 1 / math.sqrt(5), 1],
+           4: [-1, -math.sqrt(3 / 7), 0, math.sqrt(3 / 7), 1]}[p]
+    np.testing.assert_allclose(oh.gll_points(p), ref, rtol=0, atol=2 * U)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_gll_points_are_roots_of_legendre_derivative(p):
+    x = oh.gll_points(p)
+    c = np.zeros(p + 1)
+    c[p] = 1.0
+    dP = np.polynomial.legendre.legder(c)
+    assert np.abs(np.polynomial.legendre.legval(x[1:-1], dP)).max() < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_1d_operators_exact(p):
+    o = oh.operators_1d(p)
+    x, D, M, lift = o["x"], o["D"], o["M"], o["lift"]
+    for k in range(p + 1):
+        u, du = x ** k, k * x ** max(k - 1, 0)
+        assert np.all(np.abs(D @ u - du) <= (p + 8) * U * (np.abs(D) @ np.abs(u) + np.abs(du)))
+        for m in range(p + 1):
+            exact = 2.0 / (k + m + 1) if (k + m) % 2 == 0 else 0.0
+            assert abs(x ** k @ M @ x ** m - exact) <= 8 * (p + 1) ** 2 * U
+    assert np.all(np.abs(D.sum(axis=1)) <= (p + 1) * U * np.abs(D).sum(axis=1))
+    e = np.zeros((p + 1, 2))
+    e[0, 0] = e[p, 1] = 1.0
+    assert np.all(np.abs(M @ lift - e) <= (p + 4) * U * (np.abs(M) @ np.abs(lift) + 1))
+
+
+def _unfactored_rhs(p, gr, q, gamma=oe.GAMMA):
+    """The same right-hand side per element from the unfactored 3-D operators
+    (explicit D_r, D_s, D_t, LIFT3 = M3^-1 E3) and loops over elements, faces
+    and face nodes with explicit neighbour lookups."""
+    F = oh.full_operators(p)
+    P = p + 1
+    nx, ny, nz = gr["dims"]
+    out = np.zeros_like(q)
+    idx = np.arange(P ** 3).reshape(P, P, P)  # [c, b, a]
+
+    def flux(qn):
+        (Fx, Fy, Fz), (u, v, w), c = oe._fluxes(qn, gamma)
+        return (Fx, Fy, Fz), (u, v, w), c
+
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                e = i + nx * (j + ny * k)
+                h = (gr["h"][0][i], gr["h"][1][j], gr["h"][2][k])
+                Fd, _, _ = flux(q[:, e])
+                vol = sum((2.0 / h[d]) * (Fd[d] @ Dm.T) for d, Dm in enumerate((F["Dr"], F["Ds"], F["Dt"])))
+                surf = np.zeros((5, P ** 3))
+                for d in range(3):
+                    for side in (0, 1):
+                        f = 2 * d + side
+                        ijk = [i, j, k]
+                        ijk[d] = (ijk[d] + (1 if side else -1)) % (nx, ny, nz)[d]
+                        en = ijk[0] + nx * (ijk[1] + ny * ijk[2])
+                        own = np.take(idx, 0 if side == 0 else P - 1, axis=2 - d).ravel()
+                        nbr = np.take(idx, P - 1 if side == 0 else 0, axis=2 - d).ravel()
+                        n = np.zeros(3)
+                        n[d] = 1.0 if side else -1.0
+                        delta = np.zeros((5, P * P))
+                        for m in range(P * P):
+                            qm, qp = q[:, e, own[m]], q[:, en, nbr[m]]
+                            (FM, uM, cM), (FP, uP, cP) = flux(qm), flux(qp)
+                            lam = max(abs(uM[d]) + cM, abs(uP[d]) + cP)
+                            delta[:, m] = 0.5 * n[d] * (FM[d] - FP[d]) - 0.5 * lam * (qm - qp)
+                        surf += (2.0 / h[d]) * delta @ F["LIFT3"][:, f * P * P:(f + 1) * P * P].T
+                out[:, e] = -vol + surf
+    return out
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_factored_rhs_equals_unfactored_definition(p):
+    ops, gr, X = _setup(p, dims=(3, 2, 2))
+    q = wl.vortex_state(X, pert=wl.density_perturbation(3))
+    q = q * (1.0 + 1e-2 * np.random.default_rng(2).standard_normal(q.shape))
+    r = oh.rhs(ops, gr, q)
+    ref = _unfactored_rhs(p, gr, q)
+    T = oh.rhs_term_magnitude(ops, gr, q)
+    # the unfactored LIFT3 is an FP64 solve (a few u of conditioning)
+    assert np.all(np.abs(r - ref) <= 64 * (p + 1) * U * T)
+
+
+def test_free_stream_preservation(hexp):
+    ops, gr, X = hexp
+    q = wl.constant_state(X.shape[:2])
+    r = oh.rhs(ops, gr, q)
+    T = oh.rhs_term_magnitude(ops, gr, q)
+    assert np.all(np.abs(r) <= oh.contraction_length(ops["p"]) * U * T)
+
+
+def test_discrete_conservation(hexp):
+    ops, gr, X = hexp
+    q = wl.vortex_state(X, pert=wl.density_perturbation(7))
+    q = q * (1.0 + 1e-3 * np.random.default_rng(3).standard_normal(q.shape))
+    r = oh.rhs(ops, gr, q)
+    M3 = np.kron(ops["M"], np.kron(ops["M"], ops["M"]))
+    nx, ny, nz = gr["dims"]
+    J = (np.multiply.outer(np.multiply.outer(gr["h"][2], gr["h"][1]), gr["h"][0]) / 8.0).ravel()
+    w = J[None, :, None] * (r @ M3.T)
+    tot = w.sum(axis=(1, 2))
+    scale = np.abs(w).sum(axis=(1, 2))
+    assert np.all(np.abs(tot) <= 1e-13 * scale)
+
+
+def test_term_magnitude_bounds_rhs_and_fp64_error(hexp):
+    """|rhs| <= T, and the FP64 oracle against the same evaluation in extended
+    precision stays within K u T per entry."""
+    ops, gr, X = hexp
+    q = wl.vortex_state(X, pert=wl.density_perturbation(3))
+    q = q * (1.0 + 1e-2 * np.random.default_rng(5).standard_normal(q.shape))
+    r = oh.rhs(ops, gr, q)
+    T = oh.rhs_term_magnitude(ops, gr, q)
+    assert np.all(np.abs(r) <= T * (1 + 1e-12))
+    ld = np.longdouble
+    o_ld = {k: (v.astype(ld) if isinstance(v, np.ndarray) else v) for k, v in ops.items()}
+    g_ld = dict(gr, h=[h.astype(ld) for h in gr["h"]])
+    r_ext = oh.rhs(o_ld, g_ld, q.astype(ld), gamma=ld(oe.GAMMA)).astype(np.float64)
+    ratio = np.abs(r - r_ext) / T
+    assert ratio.max() <= oh.contraction_length(ops["p"]) * U
+
+
+def test_entropy_wave_linearity(hexp):
+    ops, gr, X = hexp
+    vel = np.array([0.4, -0.25, 0.15])
+    rho_fn = lambda x: 1.0 + 0.3 * np.sin(2 * np.pi * x[..., 0] / 10) * np.cos(2 * np.pi * (x[..., 1] + 2 * x[..., 2]) / 10)
+    q = wl.entropy_wave_state(X, rho_fn, vel=tuple(vel))
+    r = oh.rhs(ops, gr, q)
+    scale = np.abs(r[0]).max()
+    for d in range(3):
+        np.testing.assert_allclose(r[1 + d], vel[d] * r[0], atol=1e-12 * scale)
+    np.testing.assert_allclose(r[4], 0.5 * vel @ vel * r[0], atol=1e-12 * scale)
+
+
+def test_volume_term_exact_for_polynomial_density(hexp):
+    """A density of degree p in each coordinate (a tensor polynomial) has an
+    exactly interpolated flux, so the volume term is -u.grad rho exactly."""
+    ops, gr, X = hexp
+    p = ops["p"]
+    vel = np.array([0.4, -0.25, 0.15])
+    f = lambda x: 2.0 + (x[..., 0] / 10) ** p * (1 + (x[..., 1] / 10) ** p) + (x[..., 2] / 10) ** p
+    grad = lambda x: (vel[0] * p * (x[..., 0] / 10) ** (p - 1) / 10 * (1 + (x[..., 1] / 10) ** p)
+                      + vel[1] * (x[..., 0] / 10) ** p * p * (x[..., 1] / 10) ** (p - 1) / 10
+                      + vel[2] * p * (x[..., 2] / 10) ** (p - 1) / 10)
+    q = wl.entropy_wave_state(X, f, vel=tuple(vel))
+    _, vol, _ = oh.rhs(ops, gr, q, split=True)
+    np.testing.assert_allclose(vol[0], grad(X), atol=1e-12 * max(1.0, np.abs(grad(X)).max()))
+
+
+def test_lax_friedrichs_dissipation_identity(hexp):
+    """Discontinuous density at rest (u = 0, p constant): the volume flux
+    vanishes and d/dt 1/2 int rho^2 = -1/4 sum over faces seen from both
+    sides of sJ [rho]^T M_f (lam [rho])."""
+    ops, gr, X = hexp
+    p = ops["p"]
+    P = p + 1
+    rng = np.random.default_rng(11)
+    rho_nodes = rng.uniform(0.8, 1.2, size=X.shape[:2])
+    q = wl.entropy_wave_state(X, lambda x: rho_nodes, vel=(0.0, 0.0, 0.0), p=1.0)
+    r = oh.rhs(ops, gr, q)
+    M3 = np.kron(ops["M"], np.kron(ops["M"], ops["M"]))
+    nx, ny, nz = gr["dims"]
+    hz, hy, hx = np.meshgrid(gr["h"][2], gr["h"][1], gr["h"][0], indexing="ij")
+    J = (hx * hy * hz / 8.0).ravel()
+    lhs = np.sum(J[:, None] * q[0] * (r[0] @ M3.T))
+    rho = q[0].reshape(nz, ny, nx, P, P, P)
+    Mf = np.kron(ops["M"], ops["M"])
+    c = lambda rr: np.sqrt(1.4 * 1.0 / rr)
+    total = 0.0
+    for d, (hA, hB) in enumerate(((hy, hz), (hx, hz), (hx, hy))):
+        sJ = (hA * hB / 4.0)
+        for side in (0, 1):
+            own = np.take(rho, 0 if side == 0 else P - 1, axis=5 - d)
+            nbr = np.take(np.roll(rho, 1 if side == 0 else -1, axis=2 - d), P - 1 if side == 0 else 0, axis=5 - d)
+            jump = (own - nbr).reshape(nz, ny, nx, P * P)
+            lam = np.maximum(c(own), c(nbr)).reshape(nz, ny, nx, P * P)
+            total += np.sum(sJ * np.einsum("kjim,mn,kjin->kji", jump, Mf, lam * jump))
+    assert lhs < 0
+    assert abs(lhs - (-0.25 * total)) < 1e-12 * abs(lhs)
+
+
+def _window_l2(ops, gr, X, e, T):
+    uinf = 0.5 * math.sqrt(1.4)
+    cen = X.mean(axis=1)
+    dx = (cen[:, 0] - (5 + uinf * T) + 5) % 10 - 5
+    dy = cen[:, 1] - 5
+    m = dx * dx + dy * dy < 2.5 ** 2
+    M3 = np.kron(ops["M"], np.kron(ops["M"], ops["M"]))
+    nx, ny, nz = gr["dims"]
+    hz, hy, hx = np.meshgrid(gr["h"][2], gr["h"][1], gr["h"][0], indexing="ij")
+    J = (hx * hy * hz / 8.0).ravel()
+    return math.sqrt(np.sum(J[m] * np.einsum("ei,ij,ej->e", e[m], M3, e[m])))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("p,bound", [(2, 5e-3), (3, 1e-3)])
+def test_vortex_convergence_order(p, bound):
+    """LSRK(5,4) + DG evolution of the isentropic vortex (core radius 1.5) on
+    jittered rectilinear slabs converges at close to order p + 1 (pin:
+    order >= p + 0.3 between 8^2 and 16^2 cells, and a small absolute error)."""
+    T, R = 0.1, 1.5
+    errs = []
+    for n in (8, 16):
+        gr = oh.grid(*wl.rectilinear_grid((n, n, 2), (10.0, 10.0, 10.0 * 2 / n), 0.1, 7))
+        ops = oh.operators_1d(p)
+        X = oh.node_coordinates(gr, p)
+        q = wl.vortex_state(X, radius=R)
+        dt = oh.cfl_dt(gr, q, p, 0.4)
+        nst = int(math.ceil(T / dt))
+        dt = T / nst
+        f = lambda qq, tt: oh.rhs(ops, gr, qq)
+        for s in range(nst):
+            q, _ = lsrk.lsrk_step(f, q, s * dt, dt)
+        errs.append(_window_l2(ops, gr, X, (q - wl.vortex_state(X, t=T, radius=R))[0], T))
+    print(p, errs, math.log2(errs[0] / errs[1]))
+    assert math.log2(errs[0] / errs[1]) >= p + 0.3
+    assert errs[1] < bound
