@@ -151,6 +151,26 @@ dg_status dg_rhs(dg_mesh m, const dg_params* prm, dg_precision prec, const doubl
 dg_status dg_rk_step(dg_mesh m, const dg_params* prm, dg_precision prec, double* q, double* work,
                      double t, double dt, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Euler step as dg_rk_step (model 0, any contraction precision, the mesh's
+ * launch configuration, the same kernels and so the same bits), with the
+ * residual and the second state buffer in a fixed array the library holds
+ * on each GPU instead of a caller workspace.  It calls no allocator.
+ *  - Limit: the state may hold at most DG_NOALLOC_MAX_STATE doubles
+ *    (5 E Np <= 8,388,608: up to 83,886 tets at p = 3, e.g. one GPU's
+ *    82,944-tet share of the 48^3 mesh split over eight GPUs); larger
+ *    states return DG_ERR_ARG.  The array takes 2 x 64 MiB of every GPU
+ *    the library runs on, until the process ends.
+ *  - Every call on one GPU uses that GPU's one array: calls that overlap in
+ *    time on one GPU (different streams or threads) race and must be
+ *    serialised by the caller.  Nothing in the array needs clearing between
+ *    calls (the first stage does not read the old residual).
+ *  - model 1 returns DG_ERR_UNSUPPORTED. */
+#define DG_NOALLOC_MAX_STATE (8u << 20)
+dg_status dg_rk_step_noalloc(dg_mesh m, const dg_params* prm, dg_precision prec, double* q, double t, double dt,
+                             hipStream_t stream);
+
 /* Launch configuration of one mesh's RHS and Runge-Kutta kernels for one
  * contraction precision.  Results do not depend on it (bitwise). */
 typedef struct {

@@ -22,7 +22,7 @@ STATUS = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_MESH", 3: "DG_ERR_ALLOC", 4: "
 
 # every symbol include/dg.h declares
 EXPORTS = ("dg_reference_operators", "dg_mesh_create", "dg_mesh_info", "dg_mesh_nodes", "dg_mesh_face_map",
-           "dg_mesh_destroy", "dg_rhs", "dg_rk_step", "dg_lsrk_update", "dg_thermo_create", "dg_thermo_destroy",
+           "dg_mesh_destroy", "dg_rhs", "dg_rk_step", "dg_rk_step_noalloc", "dg_lsrk_update", "dg_thermo_create", "dg_thermo_destroy",
            "dg_mech_create", "dg_mech_destroy", "dg_temperature", "dg_sources", "dg_mlp_create", "dg_mlp_destroy",
            "dg_mlp_set_params", "dg_mlp_get_params", "dg_mlp_set_normalization", "dg_mlp_get_normalization",
            "dg_mlp_fit_normalization", "dg_mlp_loss_grad", "dg_mlp_train_step", "dg_mlp_predict",
@@ -84,6 +84,7 @@ def lib():
         L.dg_mesh_destroy.argtypes = [_c_p]
         L.dg_rhs.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_int, _c_p, _c_p, _c_p]
         L.dg_rk_step.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_int, _c_p, _c_p, _dbl, _dbl, _c_p]
+        L.dg_rk_step_noalloc.argtypes = [_c_p, ctypes.POINTER(_Params), ctypes.c_int, _c_p, _dbl, _dbl, _c_p]
         L.dg_lsrk_update.argtypes = [_i64, _dbl, _dbl, _dbl, _c_p, _c_p, _c_p, _c_p]
         L.dg_thermo_create.argtypes = [ctypes.c_int, _c_p, _c_p, ctypes.c_int, ctypes.POINTER(_c_p)]
         L.dg_thermo_destroy.argtypes = [_c_p]
@@ -332,6 +333,20 @@ def rk_step(mesh: Mesh, q, work, t: float, dt: float, precision: str = "fp64", g
     prm = _params(gamma)
     _check(lib().dg_rk_step(mesh.handle, ctypes.byref(prm), PRECISIONS[precision], _dev_ptr(q), _dev_ptr(work),
                             float(t), float(dt), _stream(stream)))
+    return q
+
+
+NOALLOC_MAX_STATE = 8 << 20  # doubles of state dg_rk_step_noalloc accepts (DG_NOALLOC_MAX_STATE)
+
+
+def rk_step_noalloc(mesh: Mesh, q, t: float, dt: float, precision: str = "fp64", gamma: float = 1.4, stream=None):
+    """One LSRK(5,4) step, q updated in place, with the library's fixed
+    per-GPU scratch array instead of a workspace (no allocation; at most
+    NOALLOC_MAX_STATE doubles of state; calls overlapping on one GPU race)."""
+    _check_state(mesh, q, 5, "q")
+    prm = _params(gamma)
+    _check(lib().dg_rk_step_noalloc(mesh.handle, ctypes.byref(prm), PRECISIONS[precision], _dev_ptr(q), float(t),
+                                    float(dt), _stream(stream)))
     return q
 
 
