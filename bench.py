@@ -538,6 +538,57 @@ def learned_leg(dg, wl, dev, stream, X48):
             "speedup_vs_plain": round(ms_p / ms_l, 3)}
 
 
+HEX_WORKLOADS = (("hex_vortex_pert_p4_48cubed", 48, 4), ("hex_vortex_pert_p1_120cubed", 120, 1))
+
+
+def hex_leg(dg, hexdg, wl, dev, stream, steps, warmup):
+    """Tensor-product hexahedra (the element of the paper's own vortex
+    benchmark): periodic rectilinear [0,10]^3 boxes with 5 % grid-line
+    jitter, vortex plus the seeded density perturbation, at p = 4 (48^3
+    cells) and p = 1 (120^3 cells), 13.8M nodes each.  Times the
+    sum-factorised FP64 RHS (settle, warm-up, one batch of `steps` launches
+    and five more for the spread) and the LSRK step; the roofline is HBM:
+    the state in and the rhs out, 2 x 5 x Np x 8 bytes per element."""
+    import torch
+    out = {}
+    for name, n, p in HEX_WORKLOADS:
+        lines = wl.rectilinear_box(n, 10.0, 0.05, 1002)
+        m = hexdg.HexMesh(p, *lines)
+        q = torch.from_numpy(wl.vortex_state(m.nodes(), pert=wl.density_perturbation(2002))).to(dev)
+        r = torch.empty_like(q)
+        launch = lambda: hexdg.rhs(m, q, r, stream=stream)
+        with torch.cuda.stream(stream):
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < SETTLE_S:
+                for _ in range(50):
+                    launch()
+                stream.synchronize()
+            for _ in range(warmup):
+                launch()
+            stream.synchronize()
+            batches = [_time_ms(stream, launch, steps) for _ in range(1 + REPEATS)]
+            work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
+            qs = q.clone()
+            hexdg.rk_step(m, qs, work, 0.0, 1e-4, stream=stream)
+            stream.synchronize()
+            ms_rk = _time_ms(stream, lambda: hexdg.rk_step(m, qs, work, 0.0, 1e-4, stream=stream), max(2, steps // 10))
+        dg.synchronize(0, stream)
+        ms = batches[0]
+        bytes_el = 2 * 5 * m.Np * 8
+        gbs = bytes_el * m.E / (ms * 1e-3) / 1e9
+        out[name] = {"elements": m.E, "order": p, "nodes_per_element": m.Np, "ms_per_rhs": round(ms, 5),
+                     "ms_per_rhs_spread": {"median": round(float(np.median(batches)), 5),
+                                           "min": round(min(batches), 5), "max": round(max(batches), 5)},
+                     "value": round(m.E * m.Np * NF / (ms * 1e-3) / 1e9, 3), "unit": "GDOF·fields/s",
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_elem": bytes_el,
+                                  "kernel": f"hex_rhs_kernel<{p}>"},
+                     "lsrk_step_ms": round(ms_rk, 4)}
+        del q, r, work, qs
+        m.close()
+    return out
+
+
 def iteration_histogram(iters):
     """{iterations: node count} of a Newton solve (-1 = failed)."""
     vals, counts = np.unique(iters, return_counts=True)
@@ -560,6 +611,8 @@ def main():
                     help="LSRK steps of the reduced-precision forms against the FP64 form (0: skip)")
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="cubes per side (default: the 48^3 workload)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched leg")
+    ap.add_argument("--no-hex", action="store_true", help="skip the hexahedron leg")
+    ap.add_argument("--hex-only", action="store_true", help="run only the hexahedron leg")
     ap.add_argument("--batched-only", action="store_true", help="run only the 64-mesh batched leg")
     ap.add_argument("--no-reacting", action="store_true", help="skip the reacting NS and learned-guess legs")
     ap.add_argument("--reacting-only", action="store_true", help="run only the reacting NS and learned-guess legs")
@@ -584,6 +637,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_per_launch": n * 8, "launches": 5}), flush=True)
+        return
+    if args.hex_only:
+        from paper_2512_17101_amd import hexdg
+        stream = torch.cuda.Stream(device=dev)
+        print(json.dumps({"hex": hex_leg(dg, hexdg, wl, dev, stream, args.steps, args.warmup)}), flush=True)
         return
     if args.batched_only:
         stream = torch.cuda.Stream(device=dev)
@@ -681,6 +739,10 @@ def main():
                 variants[mode]["error_vs_oracle"] = errs
     if variants:
         rec["variants"] = variants
+    if not args.no_hex:
+        from paper_2512_17101_amd import hexdg
+        torch.cuda.empty_cache()
+        rec["hex"] = hex_leg(dg, hexdg, wl, dev, stream, args.steps, args.warmup)
     if not args.no_batched:
         del outs
         torch.cuda.empty_cache()

@@ -1,0 +1,70 @@
+/*
+ * dg_hex.h — C ABI of the tensor-product hexahedron path of the MI355X nodal
+ * DG library: the element of the paper's own Euler benchmarks (Sec. 5.2:
+ * the p = 4 isentropic vortex and the p = 1 case on tensor-product
+ * elements), on periodic rectilinear grids.
+ *
+ * Conventions are those of dg.h (status codes, dg_last_error, caller-owned
+ * device buffers, asynchronous calls on the given stream, synchronous
+ * argument checks, the failure flag read by dg_synchronize).
+ *
+ * Mesh: nx x ny x nz cells; cell (i, j, k) is the axis-aligned box
+ * [gx[i], gx[i+1]] x [gy[j], gy[j+1]] x [gz[k], gz[k+1]], element id
+ * e = i + nx (j + ny k); the grid is periodic in every direction (cell
+ * nx - 1 neighbours cell 0; gx[nx] - gx[0] is the period).
+ * Element: tensor product of the p + 1 Legendre-Gauss-Lobatto points,
+ * node (a, b, c) at reference (r_a, s_b, t_c) with index
+ * a + (p + 1)(b + (p + 1) c); physical x = gx[i] + (1 + r_a)(gx[i+1] - gx[i]) / 2.
+ * State layout: q[5][E][Np] FP64, Np = (p + 1)^3, fields as in dg.h.
+ */
+#ifndef DG_HEX_H
+#define DG_HEX_H
+
+#include "dg.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_hex_mesh_s* dg_hex_mesh;
+
+/* Host tables of the order-p element (1 <= order <= 4), any output may be
+ * NULL: x [p+1] LGL points; D1 [p+1][p+1] row-major, D1[i][j] = l_j'(x_i)
+ * (l_j the Lagrange polynomials on the points); lift [p+1][2] row-major, the
+ * columns M1^{-1} e_0 and M1^{-1} e_p of the exact 1-D mass matrix
+ * M1[i][j] = int_{-1}^{1} l_i l_j.  The values are the exact ones at the
+ * FP64 points, rounded once.  DG_ERR_ARG for other orders. */
+dg_status dg_hex_reference_operators(int order, double* x, double* D1, double* lift);
+
+/* Builds the mesh on `device` from the host grid lines gx [nx+1], gy [ny+1],
+ * gz [nz+1] (copied), which must increase strictly (else DG_ERR_MESH); at
+ * most 2^31 - 1 nodes (E Np).  Synchronous; *out owns its device tables (2 / h per cell
+ * and axis, the 1-D operators). */
+dg_status dg_hex_mesh_create(int order, int nx, int ny, int nz, const double* gx, const double* gy,
+                             const double* gz, int device, dg_hex_mesh* out);
+dg_status dg_hex_mesh_info(dg_hex_mesh m, int64_t* n_elem, int* np);
+/* Physical node coordinates, host [E][Np][3]. */
+dg_status dg_hex_mesh_nodes(dg_hex_mesh m, double* xyz);
+dg_status dg_hex_mesh_destroy(dg_hex_mesh m);
+
+/* Strong-form Euler right-hand side (model 0 of dg_params; gamma > 1), FP64,
+ * of the nodal DG method on the hexahedra:
+ *   rhs = - sum_d (2 / h_d) D_d F_d + sum_faces (2 / h_d) l_side x Delta,
+ *   Delta = 1/2 n.(F(q-) - F(q+)) - 1/2 lam (q- - q+),
+ *   lam = max(|u-.n| + c-, |u+.n| + c+)   (local Lax-Friedrichs),
+ * D_d the 1-D derivative along direction d (sum factorisation) and l_side
+ * the lift column of the face's side, acting along the lines normal to the
+ * face.  q and rhs: device [5][E][Np], must not overlap.  model 1 returns
+ * DG_ERR_UNSUPPORTED. */
+dg_status dg_hex_rhs(dg_hex_mesh m, const dg_params* prm, const double* q, double* rhs, hipStream_t stream);
+
+/* One LSRK(5,4) step (Carpenter & Kennedy 1994, as dg_rk_step), q in place;
+ * work: device, at least 2 x 5 E Np doubles, not overlapping q. */
+dg_status dg_hex_rk_step(dg_hex_mesh m, const dg_params* prm, double* q, double* work, double t, double dt,
+                         hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_HEX_H */

@@ -1,0 +1,33 @@
+// Tensor-product hexahedra on a periodic rectilinear grid: host mesh record
+// and the kernel launcher.
+#pragma once
+#include "internal.hpp"
+
+namespace dg {
+
+constexpr int kHexMaxOrder = 4;
+
+struct HexMesh {
+  int device = 0;
+  int p = 0, N1 = 0, Np = 0;
+  int nx = 0, ny = 0, nz = 0;
+  int64_t E = 0;
+  std::vector<double> gx, gy, gz;  // grid lines, n + 1 per axis
+  std::vector<double> x1;          // [N1] LGL points
+  std::vector<double> D1;          // [N1][N1] D1[i][j] = l_j'(x_i)
+  std::vector<double> lift;        // [N1][2] columns M1^-1 e_0, M1^-1 e_p
+  // device
+  double* d_ih = nullptr;  // [nx + ny + nz]: 2 / h of each cell, x cells then y then z
+  double* d_op = nullptr;  // [N1 N1 | 2 N1]: D1 row-major, then lift row-major
+};
+
+// 1-D tables of order p (1..kHexMaxOrder): LGL points, D1, lift columns,
+// formed in binary128 and rounded once.  False for other orders.
+bool build_hex_1d(int p, std::vector<double>& x, std::vector<double>& D1, std::vector<double>& lift);
+
+// RHS of q on the hex mesh; with fused_lsrk the result goes through the
+// stage update (res <- a res + dt rhs; q_out <- q + b res) instead of rhs.
+dg_status launch_rhs_hex(const HexMesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
+                         double a, double b, double dt, bool fused_lsrk, hipStream_t s);
+
+}  // namespace dg

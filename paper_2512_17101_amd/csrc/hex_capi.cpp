@@ -1,0 +1,271 @@
+// C ABI of the tensor-product hexahedron path: 1-D reference tables, the
+// periodic rectilinear mesh, right-hand side and LSRK step.
+//
+// Reference element: the tensor product of the p + 1 Legendre-Gauss-Lobatto
+// points (closed forms for p <= 4), node (a, b, c) at index
+// a + (p + 1)(b + (p + 1) c).  The 1-D tables are the Lagrange derivative
+// matrix D1[i][j] = l_j'(x_i) and the lift columns M1^{-1} e_0, M1^{-1} e_p of
+// the exact 1-D mass matrix M1[i][j] = int_{-1}^{1} l_i l_j; they are formed
+// at the rounded FP64 points in IEEE binary128 and rounded once (the mass
+// matrix from the monomial Vandermonde V and the monomial Gram matrix H:
+// M1^{-1} = V H^{-1} V^T).
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "hex.hpp"
+
+namespace dg {
+
+namespace {
+
+using qd = __float128;
+
+qd qsqrt(qd a) {
+  if (a <= 0) return 0;
+  qd x = std::sqrt(static_cast<double>(a));
+  for (int k = 0; k < 2; ++k) x = 0.5 * (x + a / x);
+  return x;
+}
+
+qd qabs(qd a) { return a < 0 ? -a : a; }
+
+// Gauss-Jordan inverse with partial pivoting of a small matrix.
+bool qinvert(std::vector<qd>& A, int n) {
+  std::vector<qd> inv(static_cast<size_t>(n) * n, 0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (qabs(A[r * n + c]) > qabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0) return false;
+    for (int k = 0; k < n; ++k) { std::swap(A[c * n + k], A[piv * n + k]); std::swap(inv[c * n + k], inv[piv * n + k]); }
+    const qd d = 1 / A[c * n + c];
+    for (int k = 0; k < n; ++k) { A[c * n + k] *= d; inv[c * n + k] *= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c || A[r * n + c] == 0) continue;
+      const qd f = A[r * n + c];
+      for (int k = 0; k < n; ++k) { A[r * n + k] -= f * A[c * n + k]; inv[r * n + k] -= f * inv[c * n + k]; }
+    }
+  }
+  A.swap(inv);
+  return true;
+}
+
+}  // namespace
+
+bool build_hex_1d(int p, std::vector<double>& x, std::vector<double>& D1, std::vector<double>& lift) {
+  if (p < 1 || p > kHexMaxOrder) return false;
+  const int n = p + 1;
+  // LGL points (closed forms), rounded to FP64
+  qd xq[kHexMaxOrder + 1];
+  xq[0] = -1;
+  xq[p] = 1;
+  if (p == 2) xq[1] = 0;
+  if (p == 3) { xq[1] = -1 / qsqrt(5); xq[2] = -xq[1]; }
+  if (p == 4) { xq[1] = -qsqrt(qd(3) / 7); xq[2] = 0; xq[3] = -xq[1]; }
+  x.resize(n);
+  for (int i = 0; i < n; ++i) { x[i] = static_cast<double>(xq[i]); xq[i] = x[i]; }
+  // derivative matrix from the barycentric weights w_j = 1 / prod_{m != j} (x_j - x_m)
+  qd w[kHexMaxOrder + 1];
+  for (int j = 0; j < n; ++j) {
+    qd pr = 1;
+    for (int m = 0; m < n; ++m) if (m != j) pr *= xq[j] - xq[m];
+    w[j] = 1 / pr;
+  }
+  std::vector<qd> D(n * n, 0);
+  for (int i = 0; i < n; ++i) {
+    qd diag = 0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      D[i * n + j] = (w[j] / w[i]) / (xq[i] - xq[j]);
+      diag += 1 / (xq[i] - xq[j]);
+    }
+    D[i * n + i] = diag;
+  }
+  // lift columns: M1^{-1} e_k = V H^{-1} V^T e_k, V[i][k] = x_i^k, H[k][l] = int x^(k + l)
+  std::vector<qd> V(n * n), H(n * n);
+  for (int i = 0; i < n; ++i) {
+    qd pw = 1;
+    for (int k = 0; k < n; ++k) { V[i * n + k] = pw; pw *= xq[i]; }
+  }
+  for (int k = 0; k < n; ++k)
+    for (int l = 0; l < n; ++l) H[k * n + l] = (k + l) % 2 ? qd(0) : qd(2) / (k + l + 1);
+  if (!qinvert(H, n)) return false;
+  D1.resize(n * n);
+  for (int i = 0; i < n * n; ++i) D1[i] = static_cast<double>(D[i]);
+  lift.assign(n * 2, 0.0);
+  for (int side = 0; side < 2; ++side) {
+    const int row = side == 0 ? 0 : p;  // V^T e_row = (x_row^k)_k
+    std::vector<qd> y(n, 0);
+    for (int k = 0; k < n; ++k)
+      for (int l = 0; l < n; ++l) y[k] += H[k * n + l] * V[row * n + l];
+    for (int i = 0; i < n; ++i) {
+      qd s = 0;
+      for (int k = 0; k < n; ++k) s += V[i * n + k] * y[k];
+      lift[i * 2 + side] = static_cast<double>(s);
+    }
+  }
+  return true;
+}
+
+}  // namespace dg
+
+using namespace dg;
+
+namespace {
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+dg_status check_euler_params(const char* who, const dg_params* prm) {
+  if (!prm) return fail(DG_ERR_ARG, std::string(who) + ": params is NULL");
+  if (prm->model != 0) return fail(DG_ERR_UNSUPPORTED, std::string(who) + ": hexahedra run the Euler model (0) only");
+  if (!(prm->gamma > 1.0) || !std::isfinite(prm->gamma)) return fail(DG_ERR_ARG, std::string(who) + ": gamma must be > 1");
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" dg_status dg_hex_reference_operators(int order, double* x, double* D1, double* lift) {
+  std::vector<double> xs, Ds, ls;
+  if (!build_hex_1d(order, xs, Ds, ls)) return fail(DG_ERR_ARG, "dg_hex_reference_operators: order must be in 1..4");
+  if (x) std::memcpy(x, xs.data(), xs.size() * sizeof(double));
+  if (D1) std::memcpy(D1, Ds.data(), Ds.size() * sizeof(double));
+  if (lift) std::memcpy(lift, ls.data(), ls.size() * sizeof(double));
+  return DG_OK;
+}
+
+extern "C" dg_status dg_hex_mesh_create(int order, int nx, int ny, int nz, const double* gx, const double* gy,
+                                        const double* gz, int device, dg_hex_mesh* out) {
+  if (!out) return fail(DG_ERR_ARG, "dg_hex_mesh_create: out is NULL");
+  *out = nullptr;
+  if (order < 1 || order > kHexMaxOrder) return fail(DG_ERR_ARG, "dg_hex_mesh_create: order must be in 1..4");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(DG_ERR_ARG, "dg_hex_mesh_create: cell counts must be >= 1");
+  const int64_t E = static_cast<int64_t>(nx) * ny * nz;
+  const int64_t N1 = order + 1;
+  if (E * N1 * N1 * N1 > 0x7fffffff) return fail(DG_ERR_ARG, "dg_hex_mesh_create: more than 2^31 - 1 nodes");
+  if (!gx || !gy || !gz) return fail(DG_ERR_ARG, "dg_hex_mesh_create: null grid-line array");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(DG_ERR_ARG, "dg_hex_mesh_create: invalid device");
+  HexMesh* m = new (std::nothrow) HexMesh();
+  if (!m) return fail(DG_ERR_ALLOC, "dg_hex_mesh_create: host allocation failed");
+  auto cleanup = [&](dg_status s) { dg_hex_mesh_destroy(reinterpret_cast<dg_hex_mesh>(m)); return s; };
+  m->device = device;
+  m->p = order;
+  m->N1 = order + 1;
+  m->Np = m->N1 * m->N1 * m->N1;
+  m->nx = nx; m->ny = ny; m->nz = nz;
+  m->E = E;
+  m->gx.assign(gx, gx + nx + 1);
+  m->gy.assign(gy, gy + ny + 1);
+  m->gz.assign(gz, gz + nz + 1);
+  std::vector<double> ih;
+  ih.reserve(nx + ny + nz);
+  for (const std::vector<double>* g : {&m->gx, &m->gy, &m->gz})
+    for (size_t i = 0; i + 1 < g->size(); ++i) {
+      const double h = (*g)[i + 1] - (*g)[i];
+      if (!(h > 0.0) || !std::isfinite(h))
+        return cleanup(fail(DG_ERR_MESH, "dg_hex_mesh_create: grid lines must increase strictly"));
+      ih.push_back(2.0 / h);
+    }
+  if (!build_hex_1d(order, m->x1, m->D1, m->lift))
+    return cleanup(fail(DG_ERR_ARG, "dg_hex_mesh_create: reference tables failed"));
+  std::vector<double> op(m->D1);
+  op.insert(op.end(), m->lift.begin(), m->lift.end());
+  DeviceGuard g(device);
+  if (!g.ok) return cleanup(fail(DG_ERR_HIP, "dg_hex_mesh_create: hipSetDevice failed"));
+  auto up = [&](double** dst, const std::vector<double>& src) -> dg_status {
+    if (hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(double)) != hipSuccess)
+      return fail(DG_ERR_ALLOC, "dg_hex_mesh_create: hipMalloc failed");
+    if (hipMemcpy(*dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(DG_ERR_HIP, "dg_hex_mesh_create: hipMemcpy failed");
+    return DG_OK;
+  };
+  dg_status st = up(&m->d_ih, ih);
+  if (st == DG_OK) st = up(&m->d_op, op);
+  if (st != DG_OK) return cleanup(st);
+  *out = reinterpret_cast<dg_hex_mesh>(m);
+  return DG_OK;
+}
+
+extern "C" dg_status dg_hex_mesh_destroy(dg_hex_mesh h) {
+  if (!h) return DG_OK;
+  HexMesh* m = reinterpret_cast<HexMesh*>(h);
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(m->device);
+  hipFree(m->d_ih);
+  hipFree(m->d_op);
+  hipSetDevice(prev);
+  delete m;
+  return DG_OK;
+}
+
+extern "C" dg_status dg_hex_mesh_info(dg_hex_mesh h, int64_t* n_elem, int* np) {
+  if (!h) return fail(DG_ERR_ARG, "dg_hex_mesh_info: null mesh");
+  const HexMesh* m = reinterpret_cast<const HexMesh*>(h);
+  if (n_elem) *n_elem = m->E;
+  if (np) *np = m->Np;
+  return DG_OK;
+}
+
+extern "C" dg_status dg_hex_mesh_nodes(dg_hex_mesh h, double* xyz) {
+  if (!h || !xyz) return fail(DG_ERR_ARG, "dg_hex_mesh_nodes: null argument");
+  const HexMesh* m = reinterpret_cast<const HexMesh*>(h);
+  const int N1 = m->N1;
+  for (int k = 0; k < m->nz; ++k)
+    for (int j = 0; j < m->ny; ++j)
+      for (int i = 0; i < m->nx; ++i) {
+        const int64_t e = i + static_cast<int64_t>(m->nx) * (j + static_cast<int64_t>(m->ny) * k);
+        const double hx = m->gx[i + 1] - m->gx[i], hy = m->gy[j + 1] - m->gy[j], hz = m->gz[k + 1] - m->gz[k];
+        for (int c = 0; c < N1; ++c)
+          for (int b = 0; b < N1; ++b)
+            for (int a = 0; a < N1; ++a) {
+              double* X = xyz + (e * m->Np + a + N1 * (b + N1 * c)) * 3;
+              X[0] = m->gx[i] + 0.5 * (1.0 + m->x1[a]) * hx;
+              X[1] = m->gy[j] + 0.5 * (1.0 + m->x1[b]) * hy;
+              X[2] = m->gz[k] + 0.5 * (1.0 + m->x1[c]) * hz;
+            }
+      }
+  return DG_OK;
+}
+
+extern "C" dg_status dg_hex_rhs(dg_hex_mesh h, const dg_params* prm, const double* q, double* rhs, hipStream_t stream) {
+  if (!h) return fail(DG_ERR_ARG, "dg_hex_rhs: null mesh");
+  dg_status st = check_euler_params("dg_hex_rhs", prm);
+  if (st != DG_OK) return st;
+  if (!q || !rhs || !aligned8(q) || !aligned8(rhs)) return fail(DG_ERR_ARG, "dg_hex_rhs: null or misaligned state pointer");
+  const HexMesh& m = *reinterpret_cast<const HexMesh*>(h);
+  const size_t n = static_cast<size_t>(5) * m.E * m.Np;
+  if (rhs < q + n && q < rhs + n) return fail(DG_ERR_ARG, "dg_hex_rhs: q and rhs overlap");
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_rhs: hipSetDevice failed");
+  return launch_rhs_hex(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+}
+
+extern "C" dg_status dg_hex_rk_step(dg_hex_mesh h, const dg_params* prm, double* q, double* work, double t, double dt,
+                                    hipStream_t stream) {
+  (void)t;
+  if (!h) return fail(DG_ERR_ARG, "dg_hex_rk_step: null mesh");
+  dg_status st = check_euler_params("dg_hex_rk_step", prm);
+  if (st != DG_OK) return st;
+  if (!std::isfinite(dt)) return fail(DG_ERR_ARG, "dg_hex_rk_step: dt must be finite");
+  if (!q || !work || !aligned8(q) || !aligned8(work)) return fail(DG_ERR_ARG, "dg_hex_rk_step: null or misaligned pointer");
+  const HexMesh& m = *reinterpret_cast<const HexMesh*>(h);
+  const size_t n = static_cast<size_t>(5) * m.E * m.Np;
+  if (work < q + n && q < work + 2 * n) return fail(DG_ERR_ARG, "dg_hex_rk_step: work overlaps q");
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_rk_step: hipSetDevice failed");
+  // fused stages ping-pong between q and the second buffer (neighbouring
+  // elements still read the stage input); five stages end in the buffer
+  double* res = work;
+  double* buf[2] = {q, work + n};
+  for (int s = 0; s < 5; ++s) {
+    st = launch_rhs_hex(m, prm->gamma, buf[s & 1], nullptr, res, buf[(s + 1) & 1], kLsrkA[s], kLsrkB[s], dt, true,
+                        stream);
+    if (st != DG_OK) return st;
+  }
+  DG_HIP(hipMemcpyAsync(q, buf[1], n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  return DG_OK;
+}

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/dg.h"
+#include "../../include/dg_hex.h"
 #include "refelem.hpp"
 
 namespace dg {

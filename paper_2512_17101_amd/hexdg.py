@@ -1,0 +1,103 @@
+"""Python binding of the hexahedron entry points of libdg.so
+(include/dg_hex.h): argument marshalling only, like dg.py, whose loader,
+status check and parameter record it uses."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import dg
+
+# every symbol include/dg_hex.h declares
+EXPORTS = ("dg_hex_reference_operators", "dg_hex_mesh_create", "dg_hex_mesh_info", "dg_hex_mesh_nodes",
+           "dg_hex_mesh_destroy", "dg_hex_rhs", "dg_hex_rk_step")
+
+_c_p = ctypes.c_void_p
+_dbl = ctypes.c_double
+_done = False
+
+
+def lib():
+    """libdg.so with the hexahedron entry points' signatures set."""
+    global _done
+    L = dg.lib()
+    if not _done:
+        L.dg_hex_reference_operators.argtypes = [ctypes.c_int, _c_p, _c_p, _c_p]
+        L.dg_hex_mesh_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_p, _c_p, _c_p,
+                                         ctypes.c_int, ctypes.POINTER(_c_p)]
+        L.dg_hex_mesh_info.argtypes = [_c_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]
+        L.dg_hex_mesh_nodes.argtypes = [_c_p, _c_p]
+        L.dg_hex_mesh_destroy.argtypes = [_c_p]
+        L.dg_hex_rhs.argtypes = [_c_p, ctypes.POINTER(dg._Params), _c_p, _c_p, _c_p]
+        L.dg_hex_rk_step.argtypes = [_c_p, ctypes.POINTER(dg._Params), _c_p, _c_p, _dbl, _dbl, _c_p]
+        for name in EXPORTS:
+            getattr(L, name).restype = ctypes.c_int
+        _done = True
+    return L
+
+
+def reference_operators(order: int) -> dict:
+    n = order + 1
+    x, D1, lift = np.zeros(n), np.zeros((n, n)), np.zeros((n, 2))
+    dg._check(lib().dg_hex_reference_operators(order, dg._np_ptr(x), dg._np_ptr(D1), dg._np_ptr(lift)))
+    return {"x": x, "D": D1, "lift": lift}
+
+
+class HexMesh:
+    """Owning wrapper of a dg_hex_mesh handle (periodic rectilinear grid)."""
+
+    def __init__(self, order: int, gx, gy, gz, device: int = 0):
+        g = [np.ascontiguousarray(v, dtype=np.float64) for v in (gx, gy, gz)]
+        if any(v.ndim != 1 or v.size < 2 for v in g):
+            raise ValueError("grid lines must be 1-D arrays of at least two coordinates")
+        h = ctypes.c_void_p()
+        dg._check(lib().dg_hex_mesh_create(order, g[0].size - 1, g[1].size - 1, g[2].size - 1, dg._np_ptr(g[0]),
+                                           dg._np_ptr(g[1]), dg._np_ptr(g[2]), device, ctypes.byref(h)))
+        self._h = h
+        E, np_ = ctypes.c_int64(), ctypes.c_int()
+        dg._check(lib().dg_hex_mesh_info(h, ctypes.byref(E), ctypes.byref(np_)))
+        self.order, self.E, self.Np, self.device = order, E.value, np_.value, device
+        self.dims = tuple(v.size - 1 for v in g)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def nodes(self) -> np.ndarray:
+        out = np.zeros((self.E, self.Np, 3))
+        dg._check(lib().dg_hex_mesh_nodes(self._h, dg._np_ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dg_hex_mesh_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rhs(mesh: HexMesh, q, out, gamma: float = 1.4, stream=None):
+    """out <- Euler RHS of q on the hexahedra (both [5, E, Np] float64 device tensors)."""
+    dg._check_state(mesh, q, 5, "q")
+    dg._check_state(mesh, out, 5, "out")
+    prm = dg._params(gamma)
+    dg._check(lib().dg_hex_rhs(mesh.handle, ctypes.byref(prm), dg._dev_ptr(q), dg._dev_ptr(out), dg._stream(stream)))
+    return out
+
+
+def rk_step(mesh: HexMesh, q, work, t: float, dt: float, gamma: float = 1.4, stream=None):
+    """One LSRK(5,4) step on the hexahedra, q updated in place; work holds >= 2 state arrays."""
+    dg._check_state(mesh, q, 5, "q")
+    if work.numel() < 2 * q.numel():
+        raise ValueError("work must hold at least two state arrays")
+    if work.is_cuda and work.device.index != mesh.device:
+        raise ValueError("work lives on another device than the mesh")
+    prm = dg._params(gamma)
+    dg._check(lib().dg_hex_rk_step(mesh.handle, ctypes.byref(prm), dg._dev_ptr(q), dg._dev_ptr(work), float(t),
+                                   float(dt), dg._stream(stream)))
+    return q

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.mark.gpu
 def test_bench_json_line_small_mesh():
     cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--n", "8", "--steps", "3", "--warmup", "1",
-           "--no-batched", "--no-reacting", "--long-steps", "5", "--cpu-threads", "2"]
+           "--no-batched", "--no-reacting", "--no-hex", "--long-steps", "5", "--cpu-threads", "2"]
     print("running", " ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]

@@ -8,23 +8,39 @@ import numpy as np
 import pytest
 
 from oracle import reference_element as ore
-from paper_2512_17101_amd import dg
+from paper_2512_17101_amd import dg, hexdg
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "dg.h")).read()
-    src = regex.sub(r"/\*.*?\*/", "", src, flags=regex.S)
-    return set(regex.findall(r"\b(dg_[a-z0-9_]+)\s*\(", src))
+    out = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = regex.sub(r"/\*.*?\*/", "", src, flags=regex.S)
+            out |= set(regex.findall(r"\b(dg_[a-z0-9_]+)\s*\(", src))
+    return out
 
 
 def test_library_exports_every_declared_symbol():
-    L = dg.lib()
+    L = hexdg.lib()
     declared = _declared_functions()
-    assert declared == set(dg.EXPORTS)
+    assert declared == set(dg.EXPORTS) | set(hexdg.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_library_hex_tables_match_oracle(p):
+    """Binary128 tables rounded once against the oracle's rational ones: the
+    same correctly rounded values (zero entries may carry a residue below
+    1e-30)."""
+    from oracle import hex as oh
+    L, o = hexdg.reference_operators(p), oh.operators_1d(p)
+    u = 2.0 ** -53
+    for k in ("x", "D", "lift"):
+        assert np.all(np.abs(L[k] - o[k]) <= u * np.abs(o[k]) + 1e-30), k
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
