@@ -249,3 +249,194 @@ def full_operators(p: int) -> dict:
                     E3[node_n, f * P * P + m] = Mf[n, m]
     LIFT3 = np.linalg.solve(M3, E3)
     return dict(Dr=Dr, Ds=Ds, Dt=Dt, M3=M3, E3=E3, LIFT3=LIFT3)
+
+
+# ---------------------------------------------------------------------------
+# Overintegration: fluxes evaluated at Gauss-Legendre quadrature points.
+#
+# Reading (the paper names overintegration among what its shock cases need,
+# Sec. 5.3, and prints no formula): the weak form of the same DG method,
+#   (M rhs)_i = int_K grad l_i . F(q_h) - int_dK l_i Fhat,
+# with the nodal interpolant q_h evaluated at nq Gauss-Legendre points per
+# direction (nq = ceil(3 (p + 1) / 2), the "3/2 rule" against the aliasing
+# of quadratic nonlinearities), the fluxes and the Lax-Friedrichs flux
+# Fhat = 1/2 n.(F(q-) + F(q+)) + 1/2 lam (q- - q+) evaluated there, and the
+# integrals taken with that tensor rule.  On the box elements this factors
+# into rectangular 1-D contractions: B[k, j] = l_j(xi_k), B'[k, j] = l_j'(xi_k),
+# S = M1^{-1} B'^T W, P = M1^{-1} B^T W (both (p+1) x nq), and
+#   rhs = sum_d (2 / h_d) [ (S along d, P along the others) F_d(quad)
+#                           - sum_side l_side x (P x P) Fhat_face(quad) ].
+
+
+def oi_points(p: int) -> int:
+    """Gauss points per direction of the overintegrated form."""
+    return -(-3 * (p + 1) // 2)
+
+
+@lru_cache(maxsize=None)
+def _gauss_cached(n: int):
+    """n-point Gauss-Legendre rule, nodes and weights correctly rounded:
+    Newton on P_n in 60-digit decimal arithmetic from the FP64 roots,
+    w = 2 / ((1 - x^2) P_n'(x)^2)."""
+    from decimal import Decimal, localcontext
+    xf, _ = np.polynomial.legendre.leggauss(n)
+    xs, ws = [], []
+    with localcontext() as ctx:
+        ctx.prec = _DEC_DIGITS
+        for x0 in xf:
+            x = Decimal(float(x0))
+            for _ in range(8):
+                P0, P1 = Decimal(1), x
+                d0, d1 = Decimal(0), Decimal(1)
+                for k in range(1, n):
+                    P2 = ((2 * k + 1) * x * P1 - k * P0) / (k + 1)
+                    d2 = ((2 * k + 1) * (P1 + x * d1) - k * d0) / (k + 1)
+                    P0, P1, d0, d1 = P1, P2, d1, d2
+                x = x - P1 / d1
+            P0, P1 = Decimal(1), x
+            d0, d1 = Decimal(0), Decimal(1)
+            for k in range(1, n):
+                P2 = ((2 * k + 1) * x * P1 - k * P0) / (k + 1)
+                d2 = ((2 * k + 1) * (P1 + x * d1) - k * d0) / (k + 1)
+                P0, P1, d0, d1 = P1, P2, d1, d2
+            xs.append(float(x))
+            ws.append(float(2 / ((1 - x * x) * d1 * d1)))
+    return np.array(xs), np.array(ws)
+
+
+def gauss_rule(n: int):
+    x, w = _gauss_cached(n)
+    return x.copy(), w.copy()
+
+
+@lru_cache(maxsize=None)
+def _oi_operators_cached(p: int, nq: int):
+    o = operators_1d(p)
+    xg = [Fraction(float(v)) for v in o["x"]]
+    xq, wq = gauss_rule(nq)
+    xq = [Fraction(float(v)) for v in xq]
+    wq = [Fraction(float(v)) for v in wq]
+    n = p + 1
+    L = []
+    for j in range(n):
+        c = [Fraction(1)]
+        for m in range(n):
+            if m != j:
+                c = _poly_mul(c, [-xg[m] / (xg[j] - xg[m]), 1 / (xg[j] - xg[m])])
+        L.append(c)
+    val = lambda c, t: sum(ck * t ** k for k, ck in enumerate(c))
+    der = lambda c, t: sum(k * c[k] * t ** (k - 1) for k in range(1, len(c)))
+    B = [[val(L[j], t) for j in range(n)] for t in xq]
+    Bd = [[der(L[j], t) for j in range(n)] for t in xq]
+
+    def integral(c):
+        return sum(ck * Fraction(2, k + 1) for k, ck in enumerate(c) if k % 2 == 0)
+
+    M = [[integral(_poly_mul(L[i], L[j])) for j in range(n)] for i in range(n)]
+    BtW = [[B[k][j] * wq[k] for k in range(nq)] for j in range(n)]
+    BdtW = [[Bd[k][j] * wq[k] for k in range(nq)] for j in range(n)]
+    P_ = _solve_exact(M, BtW)
+    S_ = _solve_exact(M, BdtW)
+    to = lambda A: np.array([[float(v) for v in row] for row in A])
+    return dict(p=p, nq=nq, B=to(B), S=to(S_), P=to(P_), lift=o["lift"], xq=np.array([float(v) for v in xq]),
+                wq=np.array([float(v) for v in wq]))
+
+
+def oi_operators(p: int, nq: int = None) -> dict:
+    """Overintegration tables: B [nq, p+1], S and P [p+1, nq], lift [p+1, 2],
+    Gauss points xq and weights wq; exact at the FP64 points and weights,
+    rounded once."""
+    o = _oi_operators_cached(p, oi_points(p) if nq is None else nq)
+    return {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in o.items()}
+
+
+def _apply_axes(U, mats):
+    """Apply mats[d] (m x n) along the node axis of direction d of U [..., c, b, a]."""
+    for d, A in enumerate(mats):
+        if A is not None:
+            U = _apply_1d(A, U, d)
+    return U
+
+
+def _face_apply(U, A, d):
+    """Apply A along both remaining node axes of a face array U [..., s, f]
+    (the face of direction d: its two axes are the other two directions,
+    slower first)."""
+    U = np.moveaxis(np.tensordot(U, A, axes=([-1], [1])), -1, -1)
+    U = np.moveaxis(np.tensordot(U, A, axes=([-2], [1])), -1, -2)
+    return U
+
+
+def rhs_overintegrated(oi: dict, gr: dict, q: np.ndarray, gamma: float = GAMMA, split: bool = False):
+    """Overintegrated Euler RHS of q[5][E][Np] (see the notes above)."""
+    p = oi["p"]
+    P1 = p + 1
+    qs = _split(q, gr, p)
+    qq = _apply_axes(qs, [oi["B"]] * 3)
+    F, _, _ = _fluxes(qq, gamma)
+    vol = np.zeros_like(qs)
+    for d in range(3):
+        mats = [oi["P"]] * 3
+        mats[d] = oi["S"]
+        vol += _apply_axes(F[d], mats) * _inv_half_h(gr, d)[None]
+    surf = np.zeros_like(qs)
+    for d in range(3):
+        gax, nax = _GRID_AXIS[d], _NODE_AXIS[d]
+        for side in (0, 1):
+            own = np.take(qs, 0 if side == 0 else P1 - 1, axis=nax)
+            nbr = np.take(np.roll(qs, 1 if side == 0 else -1, axis=gax), P1 - 1 if side == 0 else 0, axis=nax)
+            qm, qp = _face_apply(own, oi["B"], d), _face_apply(nbr, oi["B"], d)
+            FM, uM, cM = _fluxes(qm, gamma)
+            FP, uP, cP = _fluxes(qp, gamma)
+            sgn = -1.0 if side == 0 else 1.0
+            lam = np.maximum(np.abs(uM[d]) + cM, np.abs(uP[d]) + cP)
+            fhat = 0.5 * sgn * (FM[d] + FP[d]) + 0.5 * lam * (qm - qp)
+            surf += _lift(_face_apply(fhat, oi["P"], d), oi["lift"][:, side], gr, d, P1)
+    out = (vol - surf).reshape(q.shape)
+    if split:
+        return out, vol.reshape(q.shape), surf.reshape(q.shape)
+    return out
+
+
+def rhs_overintegrated_term_magnitude(oi: dict, gr: dict, q: np.ndarray, gamma: float = GAMMA):
+    """Sum of the absolute products in each entry of the overintegrated RHS
+    before cancellation: the interpolation to the quadrature points taken
+    with |B| and |q|, the fluxes there by their absolute values, the volume
+    and face contractions with |S|, |P| and |lift|, the face flux's terms
+    absolutely (1/2 (|F(q-)| + |F(q+)|) + 1/2 lam (|q-| + |q+|))."""
+    p = oi["p"]
+    P1 = p + 1
+    aB, aS, aP = np.abs(oi["B"]), np.abs(oi["S"]), np.abs(oi["P"])
+    qs = _split(q, gr, p)
+    qq = _apply_axes(qs, [oi["B"]] * 3)
+    F, _, _ = _fluxes(qq, gamma)
+    # the interpolated state's own rounding scales with |B| |q|; the fluxes
+    # are products of the interpolated fields, so their magnitude is taken at
+    # the absolutely interpolated state (|B| x |B| x |B|) |q| where it is larger
+    Fa, _, _ = _fluxes(np.maximum(np.abs(qq), _apply_axes(np.abs(qs), [aB] * 3)) * np.sign(qq + (qq == 0)), gamma)
+    out = np.zeros_like(qs)
+    for d in range(3):
+        mats = [aP] * 3
+        mats[d] = aS
+        out += _apply_axes(np.maximum(np.abs(F[d]), np.abs(Fa[d])), mats) * _inv_half_h(gr, d)[None]
+    for d in range(3):
+        gax, nax = _GRID_AXIS[d], _NODE_AXIS[d]
+        for side in (0, 1):
+            own = np.take(qs, 0 if side == 0 else P1 - 1, axis=nax)
+            nbr = np.take(np.roll(qs, 1 if side == 0 else -1, axis=gax), P1 - 1 if side == 0 else 0, axis=nax)
+            qm, qp = _face_apply(own, oi["B"], d), _face_apply(nbr, oi["B"], d)
+            qma, qpa = _face_apply(np.abs(own), aB, d), _face_apply(np.abs(nbr), aB, d)
+            FM, uM, cM = _fluxes(qm, gamma)
+            FP, uP, cP = _fluxes(qp, gamma)
+            lam = np.maximum(np.abs(uM[d]) + cM, np.abs(uP[d]) + cP)
+            term = 0.5 * (np.abs(FM[d]) + np.abs(FP[d])) + 0.5 * lam * (qma + qpa)
+            out += _lift(_face_apply(term, aP, d), np.abs(oi["lift"][:, side]), gr, d, P1)
+    return out.reshape(q.shape)
+
+
+def oi_contraction_length(p: int) -> int:
+    """Longest chain of sums into one overintegrated entry: the three
+    interpolation passes (p + 1 terms each), the three projection passes (nq
+    each), the six faces' two interpolation and two projection passes."""
+    nq = oi_points(p)
+    return 3 * (p + 1) + 3 * nq + 6 + 2 * (p + 1) + 2 * nq
