@@ -63,6 +63,29 @@ dg_status dg_hex_rhs(dg_hex_mesh m, const dg_params* prm, const double* q, doubl
 dg_status dg_hex_rk_step(dg_hex_mesh m, const dg_params* prm, double* q, double* work, double t, double dt,
                          hipStream_t stream);
 
+/* Overintegrated form (the paper names overintegration among what its
+ * shock cases need, Sec. 5.3): the weak form of the same method,
+ *   (M rhs)_i = int_K grad l_i . F(q_h) - int_dK l_i Fhat,
+ *   Fhat = 1/2 n.(F(q-) + F(q+)) + 1/2 lam (q- - q+),
+ * with the nodal interpolant q_h, the fluxes and Fhat evaluated at
+ * nq = ceil(3 (p + 1) / 2) Gauss-Legendre points per direction (the "3/2
+ * rule" against the aliasing of quadratic nonlinearities).  It factors into
+ * rectangular 1-D contractions: B[k][j] = l_j(xi_k) (nq x (p+1)) to the
+ * quadrature points, and S = M1^{-1} B'^T W, P = M1^{-1} B^T W ((p+1) x nq)
+ * back to the nodes:
+ *   rhs = sum_d (2 / h_d) [ (S along d, P along the others) F_d(quad)
+ *                           - sum_side l_side x (P x P) Fhat_face(quad) ].
+ * Host tables for tests (any output may be NULL): *nq, the Gauss points
+ * xq [nq] and weights wq [nq] (correctly rounded), and tables =
+ * [B (nq x (p+1)) | S ((p+1) x nq) | P ((p+1) x nq) | lift ((p+1) x 2)],
+ * row-major, exact at the FP64 points and weights and rounded once. */
+dg_status dg_hex_oi_operators(int order, int* nq, double* xq, double* wq, double* tables);
+/* The overintegrated right-hand side and LSRK step; arguments and rules as
+ * dg_hex_rhs / dg_hex_rk_step. */
+dg_status dg_hex_rhs_oi(dg_hex_mesh m, const dg_params* prm, const double* q, double* rhs, hipStream_t stream);
+dg_status dg_hex_rk_step_oi(dg_hex_mesh m, const dg_params* prm, double* q, double* work, double t, double dt,
+                            hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,11 +19,27 @@ struct HexMesh {
   // device
   double* d_ih = nullptr;  // [nx + ny + nz]: 2 / h of each cell, x cells then y then z
   double* d_op = nullptr;  // [N1 N1 | 2 N1]: D1 row-major, then lift row-major
+  // overintegrated form: nq Gauss points per direction and the tables
+  // [B (nq x N1) | S (N1 x nq) | P (N1 x nq) | lift (N1 x 2)], row-major
+  int nq = 0;
+  std::vector<double> oi;
+  double* d_oi = nullptr;
 };
 
 // 1-D tables of order p (1..kHexMaxOrder): LGL points, D1, lift columns,
 // formed in binary128 and rounded once.  False for other orders.
 bool build_hex_1d(int p, std::vector<double>& x, std::vector<double>& D1, std::vector<double>& lift);
+
+// Overintegration tables of order p with nq = ceil(3 (p + 1) / 2) Gauss
+// points: points xq, weights wq and [B | S | P | lift] as in HexMesh::oi,
+// formed in binary128 at the rounded points and weights and rounded once.
+int hex_oi_points(int p);
+bool build_hex_oi(int p, std::vector<double>& xq, std::vector<double>& wq, std::vector<double>& tables);
+
+// Overintegrated RHS (weak form, fluxes at the Gauss points), optionally
+// through the fused stage update as below.
+dg_status launch_rhs_hex_oi(const HexMesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
+                            double a, double b, double dt, bool fused_lsrk, hipStream_t s);
 
 // RHS of q on the hex mesh; with fused_lsrk the result goes through the
 // stage update (res <- a res + dt rhs; q_out <- q + b res) instead of rhs.

@@ -52,6 +52,30 @@ bool qinvert(std::vector<qd>& A, int n) {
   return true;
 }
 
+// M1^{-1} of the Lagrange basis on the points x (exact 1-D mass matrix
+// int_{-1}^{1} l_i l_j): V H^{-1} V^T with V[i][k] = x_i^k and
+// H[k][l] = int x^(k + l).
+bool exact_inverse_mass(const std::vector<qd>& x, std::vector<qd>& Minv) {
+  const int n = static_cast<int>(x.size());
+  std::vector<qd> V(n * n), H(n * n);
+  for (int i = 0; i < n; ++i) {
+    qd pw = 1;
+    for (int k = 0; k < n; ++k) { V[i * n + k] = pw; pw *= x[i]; }
+  }
+  for (int k = 0; k < n; ++k)
+    for (int l = 0; l < n; ++l) H[k * n + l] = (k + l) % 2 ? qd(0) : qd(2) / (k + l + 1);
+  if (!qinvert(H, n)) return false;
+  Minv.assign(n * n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      qd s = 0;
+      for (int k = 0; k < n; ++k)
+        for (int l = 0; l < n; ++l) s += V[i * n + k] * H[k * n + l] * V[j * n + l];
+      Minv[i * n + j] = s;
+    }
+  return true;
+}
+
 }  // namespace
 
 bool build_hex_1d(int p, std::vector<double>& x, std::vector<double>& D1, std::vector<double>& lift) {
@@ -106,6 +130,85 @@ bool build_hex_1d(int p, std::vector<double>& x, std::vector<double>& D1, std::v
       lift[i * 2 + side] = static_cast<double>(s);
     }
   }
+  return true;
+}
+
+bool build_hex_oi(int p, std::vector<double>& xqd, std::vector<double>& wqd, std::vector<double>& tables) {
+  if (p < 1 || p > kHexMaxOrder) return false;
+  const int n = p + 1, nq = hex_oi_points(p);
+  std::vector<double> xg, D1, lift;
+  if (!build_hex_1d(p, xg, D1, lift)) return false;
+  // Gauss-Legendre points: Newton on P_nq from the Chebyshev-like guesses,
+  // in FP64 and then in binary128; weights 2 / ((1 - x^2) P'(x)^2)
+  auto legendre = [&](qd x, qd& Pn, qd& dPn) {
+    qd P0 = 1, P1 = x, d0 = 0, d1 = 1;
+    for (int k = 1; k < nq; ++k) {
+      const qd P2 = ((2 * k + 1) * x * P1 - k * P0) / (k + 1);
+      const qd d2 = ((2 * k + 1) * (P1 + x * d1) - k * d0) / (k + 1);
+      P0 = P1; P1 = P2; d0 = d1; d1 = d2;
+    }
+    Pn = P1;
+    dPn = d1;
+  };
+  // the rule is symmetric: the negative half by Newton, the rest mirrored,
+  // the middle point of an odd rule exactly 0
+  std::vector<qd> xq(nq), wq(nq);
+  xqd.assign(nq, 0.0);
+  wqd.assign(nq, 0.0);
+  for (int i = 0; i < (nq + 1) / 2; ++i) {
+    qd x = 0;
+    if (2 * i + 1 != nq) {
+      x = -std::cos(3.14159265358979323846 * (i + 0.75) / (nq + 0.5));
+      for (int it = 0; it < 12; ++it) {
+        qd Pn, dPn;
+        legendre(x, Pn, dPn);
+        x -= Pn / dPn;
+      }
+    }
+    qd Pn, dPn;
+    legendre(x, Pn, dPn);
+    xqd[i] = static_cast<double>(x);
+    if (2 * i + 1 != nq) xqd[nq - 1 - i] = -xqd[i];
+    wqd[i] = wqd[nq - 1 - i] = static_cast<double>(2 / ((1 - x * x) * dPn * dPn));
+  }
+  for (int i = 0; i < nq; ++i) {
+    xq[i] = xqd[i];
+    wq[i] = wqd[i];
+  }
+  // Lagrange basis on the FP64 LGL points, at the FP64 Gauss points
+  std::vector<qd> x(n);
+  for (int j = 0; j < n; ++j) x[j] = xg[j];
+  std::vector<qd> B(nq * n), Bd(nq * n);
+  for (int k = 0; k < nq; ++k)
+    for (int j = 0; j < n; ++j) {
+      qd l = 1, dl = 0;
+      for (int m = 0; m < n; ++m) {
+        if (m == j) continue;
+        const qd f = (xq[k] - x[m]) / (x[j] - x[m]);
+        dl = dl * f + l / (x[j] - x[m]);
+        l *= f;
+      }
+      B[k * n + j] = l;
+      Bd[k * n + j] = dl;
+    }
+  // S = M1^{-1} B'^T W, P = M1^{-1} B^T W with the exact mass matrix
+  // (M1^{-1} = V H^{-1} V^T, monomial Vandermonde V and Gram matrix H)
+  std::vector<qd> M;
+  if (!exact_inverse_mass(x, M)) return false;
+  tables.assign(3 * nq * n + 2 * n, 0.0);
+  for (int k = 0; k < nq; ++k)
+    for (int j = 0; j < n; ++j) tables[k * n + j] = static_cast<double>(B[k * n + j]);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < nq; ++k) {
+      qd s = 0, pp = 0;
+      for (int j = 0; j < n; ++j) {
+        s += M[i * n + j] * Bd[k * n + j] * wq[k];
+        pp += M[i * n + j] * B[k * n + j] * wq[k];
+      }
+      tables[nq * n + i * nq + k] = static_cast<double>(s);
+      tables[2 * nq * n + i * nq + k] = static_cast<double>(pp);
+    }
+  for (int i = 0; i < 2 * n; ++i) tables[3 * nq * n + i] = lift[i];
   return true;
 }
 
@@ -173,6 +276,12 @@ extern "C" dg_status dg_hex_mesh_create(int order, int nx, int ny, int nz, const
     return cleanup(fail(DG_ERR_ARG, "dg_hex_mesh_create: reference tables failed"));
   std::vector<double> op(m->D1);
   op.insert(op.end(), m->lift.begin(), m->lift.end());
+  {
+    std::vector<double> xq, wq;
+    if (!build_hex_oi(order, xq, wq, m->oi))
+      return cleanup(fail(DG_ERR_ARG, "dg_hex_mesh_create: overintegration tables failed"));
+    m->nq = hex_oi_points(order);
+  }
   DeviceGuard g(device);
   if (!g.ok) return cleanup(fail(DG_ERR_HIP, "dg_hex_mesh_create: hipSetDevice failed"));
   auto up = [&](double** dst, const std::vector<double>& src) -> dg_status {
@@ -184,6 +293,7 @@ extern "C" dg_status dg_hex_mesh_create(int order, int nx, int ny, int nz, const
   };
   dg_status st = up(&m->d_ih, ih);
   if (st == DG_OK) st = up(&m->d_op, op);
+  if (st == DG_OK) st = up(&m->d_oi, m->oi);
   if (st != DG_OK) return cleanup(st);
   *out = reinterpret_cast<dg_hex_mesh>(m);
   return DG_OK;
@@ -197,6 +307,7 @@ extern "C" dg_status dg_hex_mesh_destroy(dg_hex_mesh h) {
   hipSetDevice(m->device);
   hipFree(m->d_ih);
   hipFree(m->d_op);
+  hipFree(m->d_oi);
   hipSetDevice(prev);
   delete m;
   return DG_OK;
@@ -231,41 +342,81 @@ extern "C" dg_status dg_hex_mesh_nodes(dg_hex_mesh h, double* xyz) {
   return DG_OK;
 }
 
-extern "C" dg_status dg_hex_rhs(dg_hex_mesh h, const dg_params* prm, const double* q, double* rhs, hipStream_t stream) {
-  if (!h) return fail(DG_ERR_ARG, "dg_hex_rhs: null mesh");
-  dg_status st = check_euler_params("dg_hex_rhs", prm);
+namespace {
+
+dg_status hex_rhs_form(dg_hex_mesh h, const dg_params* prm, const double* q, double* rhs, hipStream_t stream, bool oi) {
+  const char* who = oi ? "dg_hex_rhs_oi" : "dg_hex_rhs";
+  if (!h) return fail(DG_ERR_ARG, std::string(who) + ": null mesh");
+  dg_status st = check_euler_params(who, prm);
   if (st != DG_OK) return st;
-  if (!q || !rhs || !aligned8(q) || !aligned8(rhs)) return fail(DG_ERR_ARG, "dg_hex_rhs: null or misaligned state pointer");
+  if (!q || !rhs || !aligned8(q) || !aligned8(rhs))
+    return fail(DG_ERR_ARG, std::string(who) + ": null or misaligned state pointer");
   const HexMesh& m = *reinterpret_cast<const HexMesh*>(h);
   const size_t n = static_cast<size_t>(5) * m.E * m.Np;
-  if (rhs < q + n && q < rhs + n) return fail(DG_ERR_ARG, "dg_hex_rhs: q and rhs overlap");
+  if (rhs < q + n && q < rhs + n) return fail(DG_ERR_ARG, std::string(who) + ": q and rhs overlap");
   DeviceGuard g(m.device);
-  if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_rhs: hipSetDevice failed");
-  return launch_rhs_hex(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+  if (!g.ok) return fail(DG_ERR_HIP, std::string(who) + ": hipSetDevice failed");
+  return oi ? launch_rhs_hex_oi(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream)
+            : launch_rhs_hex(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
 }
 
-extern "C" dg_status dg_hex_rk_step(dg_hex_mesh h, const dg_params* prm, double* q, double* work, double t, double dt,
-                                    hipStream_t stream) {
-  (void)t;
-  if (!h) return fail(DG_ERR_ARG, "dg_hex_rk_step: null mesh");
-  dg_status st = check_euler_params("dg_hex_rk_step", prm);
+dg_status hex_step_form(dg_hex_mesh h, const dg_params* prm, double* q, double* work, double dt, hipStream_t stream,
+                        bool oi) {
+  const char* who = oi ? "dg_hex_rk_step_oi" : "dg_hex_rk_step";
+  if (!h) return fail(DG_ERR_ARG, std::string(who) + ": null mesh");
+  dg_status st = check_euler_params(who, prm);
   if (st != DG_OK) return st;
-  if (!std::isfinite(dt)) return fail(DG_ERR_ARG, "dg_hex_rk_step: dt must be finite");
-  if (!q || !work || !aligned8(q) || !aligned8(work)) return fail(DG_ERR_ARG, "dg_hex_rk_step: null or misaligned pointer");
+  if (!std::isfinite(dt)) return fail(DG_ERR_ARG, std::string(who) + ": dt must be finite");
+  if (!q || !work || !aligned8(q) || !aligned8(work)) return fail(DG_ERR_ARG, std::string(who) + ": null or misaligned pointer");
   const HexMesh& m = *reinterpret_cast<const HexMesh*>(h);
   const size_t n = static_cast<size_t>(5) * m.E * m.Np;
-  if (work < q + n && q < work + 2 * n) return fail(DG_ERR_ARG, "dg_hex_rk_step: work overlaps q");
+  if (work < q + n && q < work + 2 * n) return fail(DG_ERR_ARG, std::string(who) + ": work overlaps q");
   DeviceGuard g(m.device);
-  if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_rk_step: hipSetDevice failed");
+  if (!g.ok) return fail(DG_ERR_HIP, std::string(who) + ": hipSetDevice failed");
   // fused stages ping-pong between q and the second buffer (neighbouring
   // elements still read the stage input); five stages end in the buffer
   double* res = work;
   double* buf[2] = {q, work + n};
   for (int s = 0; s < 5; ++s) {
-    st = launch_rhs_hex(m, prm->gamma, buf[s & 1], nullptr, res, buf[(s + 1) & 1], kLsrkA[s], kLsrkB[s], dt, true,
-                        stream);
+    st = oi ? launch_rhs_hex_oi(m, prm->gamma, buf[s & 1], nullptr, res, buf[(s + 1) & 1], kLsrkA[s], kLsrkB[s], dt,
+                                true, stream)
+            : launch_rhs_hex(m, prm->gamma, buf[s & 1], nullptr, res, buf[(s + 1) & 1], kLsrkA[s], kLsrkB[s], dt, true,
+                             stream);
     if (st != DG_OK) return st;
   }
   DG_HIP(hipMemcpyAsync(q, buf[1], n * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return DG_OK;
+}
+
+}  // namespace
+
+extern "C" dg_status dg_hex_rhs(dg_hex_mesh h, const dg_params* prm, const double* q, double* rhs, hipStream_t stream) {
+  return hex_rhs_form(h, prm, q, rhs, stream, false);
+}
+
+extern "C" dg_status dg_hex_rhs_oi(dg_hex_mesh h, const dg_params* prm, const double* q, double* rhs,
+                                   hipStream_t stream) {
+  return hex_rhs_form(h, prm, q, rhs, stream, true);
+}
+
+extern "C" dg_status dg_hex_rk_step_oi(dg_hex_mesh h, const dg_params* prm, double* q, double* work, double t,
+                                       double dt, hipStream_t stream) {
+  (void)t;
+  return hex_step_form(h, prm, q, work, dt, stream, true);
+}
+
+extern "C" dg_status dg_hex_oi_operators(int order, int* nq, double* xq, double* wq, double* tables) {
+  std::vector<double> x, w, tab;
+  if (!build_hex_oi(order, x, w, tab)) return fail(DG_ERR_ARG, "dg_hex_oi_operators: order must be in 1..4");
+  if (nq) *nq = static_cast<int>(x.size());
+  if (xq) std::memcpy(xq, x.data(), x.size() * sizeof(double));
+  if (wq) std::memcpy(wq, w.data(), w.size() * sizeof(double));
+  if (tables) std::memcpy(tables, tab.data(), tab.size() * sizeof(double));
+  return DG_OK;
+}
+
+extern "C" dg_status dg_hex_rk_step(dg_hex_mesh h, const dg_params* prm, double* q, double* work, double t, double dt,
+                                    hipStream_t stream) {
+  (void)t;
+  return hex_step_form(h, prm, q, work, dt, stream, false);
 }

@@ -11,7 +11,8 @@ from . import dg
 
 # every symbol include/dg_hex.h declares
 EXPORTS = ("dg_hex_reference_operators", "dg_hex_mesh_create", "dg_hex_mesh_info", "dg_hex_mesh_nodes",
-           "dg_hex_mesh_destroy", "dg_hex_rhs", "dg_hex_rk_step")
+           "dg_hex_mesh_destroy", "dg_hex_rhs", "dg_hex_rk_step", "dg_hex_oi_operators", "dg_hex_rhs_oi",
+           "dg_hex_rk_step_oi")
 
 _c_p = ctypes.c_void_p
 _dbl = ctypes.c_double
@@ -31,6 +32,9 @@ def lib():
         L.dg_hex_mesh_destroy.argtypes = [_c_p]
         L.dg_hex_rhs.argtypes = [_c_p, ctypes.POINTER(dg._Params), _c_p, _c_p, _c_p]
         L.dg_hex_rk_step.argtypes = [_c_p, ctypes.POINTER(dg._Params), _c_p, _c_p, _dbl, _dbl, _c_p]
+        L.dg_hex_oi_operators.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_p, _c_p, _c_p]
+        L.dg_hex_rhs_oi.argtypes = [_c_p, ctypes.POINTER(dg._Params), _c_p, _c_p, _c_p]
+        L.dg_hex_rk_step_oi.argtypes = [_c_p, ctypes.POINTER(dg._Params), _c_p, _c_p, _dbl, _dbl, _c_p]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int
         _done = True
@@ -42,6 +46,18 @@ def reference_operators(order: int) -> dict:
     x, D1, lift = np.zeros(n), np.zeros((n, n)), np.zeros((n, 2))
     dg._check(lib().dg_hex_reference_operators(order, dg._np_ptr(x), dg._np_ptr(D1), dg._np_ptr(lift)))
     return {"x": x, "D": D1, "lift": lift}
+
+
+def oi_operators(order: int) -> dict:
+    """Overintegration tables: nq, Gauss points xq and weights wq, B, S, P, lift."""
+    n = order + 1
+    nq = ctypes.c_int()
+    dg._check(lib().dg_hex_oi_operators(order, ctypes.byref(nq), None, None, None))
+    k = nq.value
+    xq, wq, tab = np.zeros(k), np.zeros(k), np.zeros(3 * k * n + 2 * n)
+    dg._check(lib().dg_hex_oi_operators(order, ctypes.byref(nq), dg._np_ptr(xq), dg._np_ptr(wq), dg._np_ptr(tab)))
+    return {"nq": k, "xq": xq, "wq": wq, "B": tab[:k * n].reshape(k, n), "S": tab[k * n:2 * k * n].reshape(n, k),
+            "P": tab[2 * k * n:3 * k * n].reshape(n, k), "lift": tab[3 * k * n:].reshape(n, 2)}
 
 
 class HexMesh:
@@ -90,14 +106,26 @@ def rhs(mesh: HexMesh, q, out, gamma: float = 1.4, stream=None):
     return out
 
 
-def rk_step(mesh: HexMesh, q, work, t: float, dt: float, gamma: float = 1.4, stream=None):
-    """One LSRK(5,4) step on the hexahedra, q updated in place; work holds >= 2 state arrays."""
+def rhs_oi(mesh: HexMesh, q, out, gamma: float = 1.4, stream=None):
+    """out <- overintegrated Euler RHS of q (Gauss-point flux evaluation)."""
+    dg._check_state(mesh, q, 5, "q")
+    dg._check_state(mesh, out, 5, "out")
+    prm = dg._params(gamma)
+    dg._check(lib().dg_hex_rhs_oi(mesh.handle, ctypes.byref(prm), dg._dev_ptr(q), dg._dev_ptr(out),
+                                  dg._stream(stream)))
+    return out
+
+
+def rk_step(mesh: HexMesh, q, work, t: float, dt: float, gamma: float = 1.4, overintegrate: bool = False, stream=None):
+    """One LSRK(5,4) step on the hexahedra, q updated in place; work holds >=
+    2 state arrays; overintegrate selects the Gauss-point flux evaluation."""
     dg._check_state(mesh, q, 5, "q")
     if work.numel() < 2 * q.numel():
         raise ValueError("work must hold at least two state arrays")
     if work.is_cuda and work.device.index != mesh.device:
         raise ValueError("work lives on another device than the mesh")
     prm = dg._params(gamma)
-    dg._check(lib().dg_hex_rk_step(mesh.handle, ctypes.byref(prm), dg._dev_ptr(q), dg._dev_ptr(work), float(t),
-                                   float(dt), dg._stream(stream)))
+    fn = lib().dg_hex_rk_step_oi if overintegrate else lib().dg_hex_rk_step
+    dg._check(fn(mesh.handle, ctypes.byref(prm), dg._dev_ptr(q), dg._dev_ptr(work), float(t), float(dt),
+                 dg._stream(stream)))
     return q

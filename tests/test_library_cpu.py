@@ -86,3 +86,20 @@ def test_host_side_argument_checks_need_no_device():
     assert L.dg_lsrk_update(0, 0.0, 1.0, 1e-3, None, None, None, None) == 0  # nothing to do
     # destroying null handles is a no-op
     assert L.dg_batch_destroy(None) == 0
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_library_hex_oi_tables_match_oracle(p):
+    """Gauss points and weights correctly rounded on both sides, and the
+    overintegration tables exact at them and rounded once: the same values,
+    except that an entry whose exact value is a rounding tie (a product such
+    as 1.5 x an FP64 weight needs 54 bits) may round either way under the
+    binary128 route's last-bit error: one unit in the last place allowed."""
+    from oracle import hex as oh
+    L, o = hexdg.oi_operators(p), oh.oi_operators(p)
+    assert L["nq"] == o["nq"]
+    u = 2.0 ** -53
+    for k in ("xq", "wq", "B", "lift"):
+        assert np.all(np.abs(L[k] - o[k]) <= u * np.abs(o[k]) + 1e-30), k
+    for k in ("S", "P"):
+        assert np.all(np.abs(L[k] - o[k]) <= 2 * u * np.abs(o[k]) + 1e-30), k
