@@ -17,7 +17,10 @@ Modules:
                      face mass, LIFT, Fmask
   mesh               affine geometry, face normals/areas, face-node connectivity
   hex                tensor-product hexahedra: LGL nodes, 1-D operators, factored
-                     lift, Euler RHS on periodic rectilinear grids
+                     lift, Euler RHS on periodic rectilinear grids, and the
+                     overintegrated (Gauss-point) weak form
+  shock              on the hexahedra: modal smoothness indicator, artificial
+                     viscosity (BR1), positivity-preserving limiter
   euler              strong-form Euler RHS with a local Lax-Friedrichs flux
   lsrk               five-stage, fourth-order low-storage Runge-Kutta
   precision          FP32 / split-BF16 contraction emulation and error bounds

@@ -73,13 +73,17 @@ def butcher_tableau():
     return Amat, bvec, Amat.sum(axis=1)
 
 
-def lsrk_step(f, q: np.ndarray, t: float, dt: float):
-    """One LSRK(5,4) step of dq/dt = f(q, t); returns (q_new, res)."""
+def lsrk_step(f, q: np.ndarray, t: float, dt: float, stage_filter=None):
+    """One LSRK(5,4) step of dq/dt = f(q, t); returns (q_new, res).
+    stage_filter (optional) maps every stage state to the one the next stage
+    uses (a limiter); the residual is left as it is."""
     q = q.copy()
     res = np.zeros_like(q)
     for s in range(5):
         res = A[s] * res + dt * f(q, t + C[s] * dt)
         q = q + B[s] * res
+        if stage_filter is not None:
+            q = stage_filter(q)
     return q, res
 
 

@@ -318,3 +318,17 @@ def reacting_state(xyz, seed: int = 3005, L: float = 0.01, n_cells: int = 32):
     E = rho * (e + 0.5 * (u * u + v * v + w * w))
     q = np.concatenate([np.stack([rho, rho * u, rho * v, rho * w, E]), rho[None] * Y], axis=0)
     return np.ascontiguousarray(q)
+
+
+def shock_slab_state(xyz, rho_in: float = 120.0, rho_out: float = 1.2, x0: float = 2.5, x1: float = 7.5,
+                     ripple: float = 0.3, L: float = 10.0, gamma: float = GAMMA):
+    """Gas at rest with a density discontinuity: rho_in inside the slab
+    x0 + r(y, z) < x < x1 + r(y, z), rho_out outside, r a rippled interface
+    offset ripple sin(2 pi y / L) cos(2 pi z / L), and the pressure of the
+    isentropic relation p = rho / gamma (the initial condition of the
+    paper's shock / boundary-layer case, Sec. 5.3, on a periodic box)."""
+    r = ripple * np.sin(2 * math.pi * xyz[..., 1] / L) * np.cos(2 * math.pi * xyz[..., 2] / L)
+    x = xyz[..., 0]
+    rho = np.where((x > x0 + r) & (x < x1 + r), rho_in, rho_out)
+    zero = np.zeros_like(rho)
+    return np.ascontiguousarray(primitive_to_conserved(rho, zero, zero, zero, rho / gamma, gamma))
