@@ -623,6 +623,59 @@ def hex_leg(dg, hexdg, wl, dev, stream, steps, warmup):
     return out
 
 
+SHOCK_WORKLOADS = (("hex_shock_slab_p1_120cubed", 120, 1), ("hex_shock_slab_p4_48cubed", 48, 4))
+
+
+def shock_leg(dg, hexdg, wl, dev, stream, steps, warmup):
+    """Shock capturing on the hexahedra: the density slab at rest (ratio 100,
+    p = rho / gamma, rippled interfaces) on periodic rectilinear [0,10]^3
+    boxes with 5 % grid-line jitter, p = 1 (120^3 cells, the paper's shock
+    cases use degree-1 tensor-product elements) and p = 4 (48^3).  Times
+    the indicator + viscous-flux kernel, the RHS with artificial viscosity,
+    the limiter, and the LSRK step with viscosity and stage limiting against
+    the plain step."""
+    import torch
+    out = {}
+    for name, n, p in SHOCK_WORKLOADS:
+        lines = wl.rectilinear_box(n, 10.0, 0.05, 1002)
+        m = hexdg.HexMesh(p, *lines)
+        q = torch.from_numpy(wl.shock_slab_state(m.nodes())).to(dev)
+        r = torch.empty_like(q)
+        nn = m.E * m.Np
+        G = torch.empty((3, 5, m.E, m.Np), dtype=torch.float64, device=dev)
+        eps = torch.empty(m.E, dtype=torch.float64, device=dev)
+        work = torch.empty(hexdg.SHOCK_STEP_WORK * nn + 2 * m.E, dtype=torch.float64, device=dev)
+        wplain = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
+        av = hexdg.av_params(p)
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                hexdg.av_rhs(m, q, r, work, av, stream=stream)
+            stream.synchronize()
+            ms_flux = _time_ms(stream, lambda: hexdg.av_viscosity(m, q, G, None, eps, av, stream=stream), steps)
+            ms_rhs = _time_ms(stream, lambda: hexdg.av_rhs(m, q, r, work, av, stream=stream), steps)
+            ms_plain = _time_ms(stream, lambda: hexdg.rhs(m, q, r, stream=stream), steps)
+            ql = q.clone()
+            ms_lim = _time_ms(stream, lambda: hexdg.limit(m, ql, av, stream=stream), steps)
+            qs = q.clone()
+            dt = 1e-4
+            ms_step = _time_ms(stream, lambda: hexdg.shock_rk_step(m, qs, work, 0.0, dt, av, stream=stream),
+                               max(2, steps // 10))
+            qp = q.clone()
+            ms_pstep = _time_ms(stream, lambda: hexdg.rk_step(m, qp, wplain, 0.0, dt, stream=stream), max(2, steps // 10))
+        dg.synchronize(0, stream)
+        viscous = int((eps > 0).sum().item())
+        out[name] = {"elements": m.E, "order": p, "viscous_elements": viscous,
+                     "ms_indicator_and_viscous_flux": round(ms_flux, 4), "ms_rhs_with_av": round(ms_rhs, 4),
+                     "ms_rhs_plain": round(ms_plain, 4), "ms_limiter": round(ms_lim, 4),
+                     "ms_step_with_av_and_limiter": round(ms_step, 4), "ms_step_plain": round(ms_pstep, 4),
+                     "value": round(nn * NF / (ms_rhs * 1e-3) / 1e9, 3),
+                     "unit": "GDOF·fields/s (RHS with artificial viscosity)",
+                     "state_finite": bool(torch.isfinite(qs).all()), "min_density_after_steps": float(qs[0].min())}
+        del q, r, G, eps, work, wplain, ql, qs, qp
+        m.close()
+    return out
+
+
 def iteration_histogram(iters):
     """{iterations: node count} of a Newton solve (-1 = failed)."""
     vals, counts = np.unique(iters, return_counts=True)
@@ -646,6 +699,7 @@ def main():
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="cubes per side (default: the 48^3 workload)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched leg")
     ap.add_argument("--no-hex", action="store_true", help="skip the hexahedron leg")
+    ap.add_argument("--no-shock", action="store_true", help="skip the shock-capturing leg")
     ap.add_argument("--hex-only", action="store_true", help="run only the hexahedron leg")
     ap.add_argument("--batched-only", action="store_true", help="run only the 64-mesh batched leg")
     ap.add_argument("--no-reacting", action="store_true", help="skip the reacting NS and learned-guess legs")
@@ -675,7 +729,10 @@ def main():
     if args.hex_only:
         from paper_2512_17101_amd import hexdg
         stream = torch.cuda.Stream(device=dev)
-        print(json.dumps({"hex": hex_leg(dg, hexdg, wl, dev, stream, args.steps, args.warmup)}), flush=True)
+        rec = {"hex": hex_leg(dg, hexdg, wl, dev, stream, args.steps, args.warmup)}
+        if not args.no_shock:
+            rec["shock"] = shock_leg(dg, hexdg, wl, dev, stream, args.steps, args.warmup)
+        print(json.dumps(rec), flush=True)
         return
     if args.batched_only:
         stream = torch.cuda.Stream(device=dev)
@@ -777,6 +834,8 @@ def main():
         from paper_2512_17101_amd import hexdg
         torch.cuda.empty_cache()
         rec["hex"] = hex_leg(dg, hexdg, wl, dev, stream, args.steps, args.warmup)
+        if not args.no_shock:
+            rec["shock"] = shock_leg(dg, hexdg, wl, dev, stream, args.steps, args.warmup)
     if not args.no_batched:
         del outs
         torch.cuda.empty_cache()

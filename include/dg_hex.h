@@ -86,6 +86,53 @@ dg_status dg_hex_rhs_oi(dg_hex_mesh m, const dg_params* prm, const double* q, do
 dg_status dg_hex_rk_step_oi(dg_hex_mesh m, const dg_params* prm, double* q, double* work, double t, double dt,
                             hipStream_t stream);
 
+/* Shock capturing (the paper names artificial viscosity and shock limiting
+ * among what its shock cases need, Sec. 5.3; the formulas below are the
+ * readings this library implements):
+ *  - indicator per element (Persson & Peraire 2006): the density's
+ *    coefficients c in the orthonormal tensor Legendre basis, S = (energy of
+ *    the modes with max(i, j, k) = p) / (total energy), s = log10 S
+ *    (-inf for S = 0);
+ *  - viscosity per element eps = c_eps h / p max(|u| + c) ramp(s), h the
+ *    element's smallest edge, ramp 0 below s0 - kappa, 1 above s0 + kappa,
+ *    (1 + sin(pi (s - s0) / (2 kappa))) / 2 between;
+ *  - d q/dt += div(eps grad q) for every conserved field, BR1 with central
+ *    fluxes: sigma_d = (2/h_d)(D_d q + sum_side l_side n_d (q+ - q-)/2),
+ *    G_d = eps sigma_d, added as sum_d (2/h_d)(D_d G_d + sum_side l_side
+ *    n_d (G_d+ - G_d-)/2);
+ *  - positivity limiter (Zhang & Shu 2010) per element on every stage
+ *    state: with the cell average qbar (weights int l_i), if min rho < delta
+ *    q <- qbar + theta1 (q - qbar), theta1 = (rhobar - delta)/(rhobar - min rho);
+ *    then if a nodal pressure p_i < delta, q <- qbar + theta2 (q - qbar),
+ *    theta2 = min (pbar - delta)/(pbar - p_i), pbar = p(qbar); averages are
+ *    kept, an element whose average is not admissible is left as it is. */
+typedef struct {
+  double s0;     /* indicator threshold (suggested -(1 + 4 log10 p)) */
+  double kappa;  /* half-width of the ramp, > 0 (suggested 1) */
+  double c_eps;  /* viscosity scale, >= 0 (suggested 0.5) */
+  double delta;  /* positivity floor of density and pressure, > 0 (suggested 1e-10) */
+} dg_av_params;
+
+/* Indicator and viscosity of q per element (s_out, eps_out: device [E]; s_out
+ * may be NULL) and the viscous fluxes G_out: device [3][5][E][Np]
+ * (direction-major), which dg_hex_av_rhs also forms.  G is written only in
+ * elements with eps > 0 (in the others it is zero and left unwritten). */
+dg_status dg_hex_av_viscosity(dg_hex_mesh m, const dg_params* prm, const dg_av_params* av, const double* q,
+                              double* s_out, double* eps_out, double* G_out, hipStream_t stream);
+/* Euler right-hand side plus the artificial-viscosity term; work: device,
+ * at least DG_HEX_AV_RHS_WORK E Np + 2 E doubles (viscous fluxes,
+ * indicator, viscosity). */
+#define DG_HEX_AV_RHS_WORK 15
+dg_status dg_hex_av_rhs(dg_hex_mesh m, const dg_params* prm, const dg_av_params* av, const double* q, double* rhs,
+                        double* work, hipStream_t stream);
+/* The positivity limiter applied to q in place (asynchronous). */
+dg_status dg_hex_limit(dg_hex_mesh m, const dg_params* prm, const dg_av_params* av, double* q, hipStream_t stream);
+/* One LSRK(5,4) step with artificial viscosity, each stage state limited;
+ * work: at least DG_HEX_SHOCK_STEP_WORK E Np + 2 E doubles. */
+#define DG_HEX_SHOCK_STEP_WORK 25
+dg_status dg_hex_shock_rk_step(dg_hex_mesh m, const dg_params* prm, const dg_av_params* av, double* q, double* work,
+                               double t, double dt, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,5 +1,8 @@
 // Strong-form nodal DG right-hand side of the Euler equations on
-// tensor-product hexahedra of a periodic rectilinear grid, FP64, gfx950.
+// tensor-product hexahedra of a periodic rectilinear grid, FP64, gfx950;
+// optionally plus the divergence of artificial-viscosity fluxes G (BR1
+// central flux: the volume term takes F - G, the face jump adds
+// n_d ((G+ + G-)/2 - G-)).
 //
 // The element is an axis-aligned box, so the volume term is three sums of
 // one-dimensional derivatives (sum factorisation: (p + 1) products per node
@@ -42,6 +45,8 @@ struct HexCfg {
 
 struct HexArgs {
   const double* __restrict__ q;
+  const double* __restrict__ G;   // artificial viscosity: viscous fluxes [3][5][E][Np], valid where eps > 0
+  const double* __restrict__ eps; // artificial viscosity per element
   double* __restrict__ rhs;
   double* __restrict__ res;
   double* __restrict__ qout;
@@ -73,8 +78,8 @@ __device__ inline void dir_flux(const double q[5], int d, double gamma, double F
   c = sqrt(gamma * p * ir);
 }
 
-template <int P, bool FUSED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (P == 4 && FUSED) ? 3 : 4))) void hex_rhs_kernel(HexArgs A) {
+template <int P, bool FUSED, bool AV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (P == 4 && FUSED) || AV ? 3 : 4))) void hex_rhs_kernel(HexArgs A) {
   using C = HexCfg<P>;
   constexpr int N1 = C::N1, NP = C::NP, NFP = C::NFP, EPB = C::EPB;
   __shared__ double s_q[EPB][5][NP];
@@ -99,6 +104,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
 #pragma unroll
   for (int f = 0; f < 5; ++f) qv[f] = A.q[f * Es + idx];
   double qp[C::KF][5];
+  double gp[AV ? C::KF : 1][5], gm[AV ? C::KF : 1][5];
   int ownn[C::KF];
 #pragma unroll
   for (int u = 0; u < C::KF; ++u) {
@@ -121,6 +127,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
     const int gi = en * NP + nn;
 #pragma unroll
     for (int f = 0; f < 5; ++f) qp[u][f] = A.q[f * Es + gi];
+    if (AV) {
+      // viscous flux of direction d at both sides of the face node (zero,
+      // and not stored, in an inviscid element)
+      const int go = ef * NP + ownn[u];
+      const bool vp = A.eps[en] > 0.0, vm = A.eps[ef] > 0.0;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        gp[u][f] = vp ? A.G[(d * 5 + f) * Es + gi] : 0.0;
+        gm[u][f] = vm ? A.G[(d * 5 + f) * Es + go] : 0.0;
+      }
+    }
   }
   if (tid < C::NOP) s_op[tid] = opv;
   if (own) {
@@ -146,7 +163,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
       dir_flux(qp[u], d, A.gamma, FP, uP, cP);
       const double lam = fmax(fabs(uM) + cM, fabs(uP) + cP);
 #pragma unroll
-      for (int f = 0; f < 5; ++f) s_D[fl][face][f][m] = sgn * (FM[f] - FP[f]) - 0.5 * lam * (qm[f] - qp[u][f]);
+      for (int f = 0; f < 5; ++f) {
+        double dj = sgn * (FM[f] - FP[f]) - 0.5 * lam * (qm[f] - qp[u][f]);
+        if (AV) dj += sgn * (gp[u][f] - gm[u][f]);  // n_d ((G+ + G-)/2 - G-)
+        s_D[fl][face][f][m] = dj;
+      }
     }
   }
 
@@ -181,9 +202,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
     if (own) {
       // flux of field f along x, y, z: q_f u_d + p delta(f, 1 + d); energy (E + p) u_d
       const double qe = f == 4 ? qf + pr : qf;
-      s_F[0][tid] = qe * vx + (f == 1 ? pr : 0.0);
-      s_F[1][tid] = qe * vy + (f == 2 ? pr : 0.0);
-      s_F[2][tid] = qe * vz + (f == 3 ? pr : 0.0);
+      double fx = qe * vx + (f == 1 ? pr : 0.0);
+      double fy = qe * vy + (f == 2 ? pr : 0.0);
+      double fz = qe * vz + (f == 3 ? pr : 0.0);
+      if (AV && A.eps[e] > 0.0) {  // total flux F - G (the viscous term enters as + div G)
+        fx -= A.G[(0 * 5 + f) * Es + idx];
+        fy -= A.G[(1 * 5 + f) * Es + idx];
+        fz -= A.G[(2 * 5 + f) * Es + idx];
+      }
+      s_F[0][tid] = fx;
+      s_F[1][tid] = fy;
+      s_F[2][tid] = fz;
     }
     __syncthreads();
     double dx = 0.0, dy = 0.0, dz = 0.0;
@@ -218,10 +247,16 @@ template <int P>
 dg_status launch_p(const HexMesh& m, const HexArgs& A, bool fused, hipStream_t s) {
   using C = HexCfg<P>;
   const int64_t blocks = (m.E + C::EPB - 1) / C::EPB;
-  if (fused)
-    hipLaunchKernelGGL((hex_rhs_kernel<P, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
-  else
-    hipLaunchKernelGGL((hex_rhs_kernel<P, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+  if (A.G) {
+    if (fused)
+      hipLaunchKernelGGL((hex_rhs_kernel<P, true, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+    else
+      hipLaunchKernelGGL((hex_rhs_kernel<P, false, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+  } else if (fused) {
+    hipLaunchKernelGGL((hex_rhs_kernel<P, true, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+  } else {
+    hipLaunchKernelGGL((hex_rhs_kernel<P, false, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+  }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? DG_OK : hip_fail(e, "hex rhs launch");
 }
@@ -230,8 +265,16 @@ dg_status launch_p(const HexMesh& m, const HexArgs& A, bool fused, hipStream_t s
 
 dg_status launch_rhs_hex(const HexMesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
                          double a, double b, double dt, bool fused, hipStream_t s) {
+  return launch_rhs_hex_av(m, gamma, q, nullptr, nullptr, rhs, res, q_out, a, b, dt, fused, s);
+}
+
+dg_status launch_rhs_hex_av(const HexMesh& m, double gamma, const double* q, const double* G, const double* eps,
+                            double* rhs, double* res, double* q_out, double a, double b, double dt, bool fused,
+                            hipStream_t s) {
   HexArgs A;
   A.q = q;
+  A.G = G;
+  A.eps = eps;
   A.rhs = rhs;
   A.res = res;
   A.qout = q_out;

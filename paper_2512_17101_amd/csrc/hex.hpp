@@ -24,6 +24,9 @@ struct HexMesh {
   int nq = 0;
   std::vector<double> oi;
   double* d_oi = nullptr;
+  // shock capturing: [Vinv (N1 x N1) | w1 (N1)], the inverse of the 1-D
+  // orthonormal Legendre Vandermonde and the 1-D weights int l_i
+  double* d_sh = nullptr;
 };
 
 // 1-D tables of order p (1..kHexMaxOrder): LGL points, D1, lift columns,
@@ -40,6 +43,23 @@ bool build_hex_oi(int p, std::vector<double>& xq, std::vector<double>& wq, std::
 // through the fused stage update as below.
 dg_status launch_rhs_hex_oi(const HexMesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
                             double a, double b, double dt, bool fused_lsrk, hipStream_t s);
+
+// Shock-capturing tables of order p: the inverse orthonormal Legendre
+// Vandermonde on the LGL points (row-major) and the weights int l_i.
+bool build_hex_shock_tables(int p, std::vector<double>& tables);
+// Indicator s (may be null), viscosity eps (required: the RHS reads it)
+// per element and the viscous fluxes G [3][5][E][Np] of q, stored only in
+// elements with eps > 0.
+dg_status launch_hex_av_flux(const HexMesh& m, const dg_av_params& av, double gamma, const double* q, double* G,
+                             double* s_out, double* eps_out, hipStream_t s);
+// Positivity limiter of q in place.
+dg_status launch_hex_limit(const HexMesh& m, const dg_av_params& av, double gamma, double* q, hipStream_t s);
+// Euler RHS plus the divergence of the viscous fluxes G (BR1 central flux;
+// G is read only in elements with eps > 0, elsewhere it is zero), optionally
+// through the fused stage update.
+dg_status launch_rhs_hex_av(const HexMesh& m, double gamma, const double* q, const double* G, const double* eps,
+                            double* rhs, double* res, double* q_out, double a, double b, double dt, bool fused_lsrk,
+                            hipStream_t s);
 
 // RHS of q on the hex mesh; with fused_lsrk the result goes through the
 // stage update (res <- a res + dt rhs; q_out <- q + b res) instead of rhs.

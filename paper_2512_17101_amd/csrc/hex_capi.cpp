@@ -212,6 +212,40 @@ bool build_hex_oi(int p, std::vector<double>& xqd, std::vector<double>& wqd, std
   return true;
 }
 
+bool build_hex_shock_tables(int p, std::vector<double>& tables) {
+  if (p < 1 || p > kHexMaxOrder) return false;
+  const int n = p + 1;
+  std::vector<double> xg, D1, lift;
+  if (!build_hex_1d(p, xg, D1, lift)) return false;
+  // orthonormal Legendre Vandermonde Vm[i][k] = sqrt((2k + 1)/2) P_k(x_i) and
+  // the monomial one (for the weights int l_i = sum_k (V^{-1})[k][i] int x^k)
+  std::vector<qd> Vm(n * n), V(n * n);
+  for (int i = 0; i < n; ++i) {
+    const qd x = xg[i];
+    qd P0 = 1, P1 = x, pw = 1;
+    for (int k = 0; k < n; ++k) {
+      const qd Pk = k == 0 ? P0 : P1;
+      Vm[i * n + k] = Pk * qsqrt(qd(2 * k + 1) / 2);
+      if (k >= 1) {
+        const qd P2 = ((2 * k + 1) * x * P1 - k * P0) / (k + 1);
+        P0 = P1;
+        P1 = P2;
+      }
+      V[i * n + k] = pw;
+      pw *= x;
+    }
+  }
+  if (!qinvert(Vm, n) || !qinvert(V, n)) return false;
+  tables.assign(n * n + n, 0.0);
+  for (int i = 0; i < n * n; ++i) tables[i] = static_cast<double>(Vm[i]);
+  for (int i = 0; i < n; ++i) {
+    qd w = 0;
+    for (int k = 0; k < n; k += 2) w += V[k * n + i] * qd(2) / (k + 1);
+    tables[n * n + i] = static_cast<double>(w);
+  }
+  return true;
+}
+
 }  // namespace dg
 
 using namespace dg;
@@ -282,6 +316,9 @@ extern "C" dg_status dg_hex_mesh_create(int order, int nx, int ny, int nz, const
       return cleanup(fail(DG_ERR_ARG, "dg_hex_mesh_create: overintegration tables failed"));
     m->nq = hex_oi_points(order);
   }
+  std::vector<double> sh;
+  if (!build_hex_shock_tables(order, sh))
+    return cleanup(fail(DG_ERR_ARG, "dg_hex_mesh_create: shock-capturing tables failed"));
   DeviceGuard g(device);
   if (!g.ok) return cleanup(fail(DG_ERR_HIP, "dg_hex_mesh_create: hipSetDevice failed"));
   auto up = [&](double** dst, const std::vector<double>& src) -> dg_status {
@@ -294,6 +331,7 @@ extern "C" dg_status dg_hex_mesh_create(int order, int nx, int ny, int nz, const
   dg_status st = up(&m->d_ih, ih);
   if (st == DG_OK) st = up(&m->d_op, op);
   if (st == DG_OK) st = up(&m->d_oi, m->oi);
+  if (st == DG_OK) st = up(&m->d_sh, sh);
   if (st != DG_OK) return cleanup(st);
   *out = reinterpret_cast<dg_hex_mesh>(m);
   return DG_OK;
@@ -308,6 +346,7 @@ extern "C" dg_status dg_hex_mesh_destroy(dg_hex_mesh h) {
   hipFree(m->d_ih);
   hipFree(m->d_op);
   hipFree(m->d_oi);
+  hipFree(m->d_sh);
   hipSetDevice(prev);
   delete m;
   return DG_OK;
@@ -419,4 +458,100 @@ extern "C" dg_status dg_hex_rk_step(dg_hex_mesh h, const dg_params* prm, double*
                                     hipStream_t stream) {
   (void)t;
   return hex_step_form(h, prm, q, work, dt, stream, false);
+}
+
+namespace {
+
+dg_status check_av(const char* who, const dg_av_params* av) {
+  if (!av) return fail(DG_ERR_ARG, std::string(who) + ": av params is NULL");
+  if (!std::isfinite(av->s0) || !(av->kappa > 0.0) || !std::isfinite(av->kappa) || !(av->c_eps >= 0.0) ||
+      !std::isfinite(av->c_eps) || !(av->delta > 0.0) || !std::isfinite(av->delta))
+    return fail(DG_ERR_ARG, std::string(who) + ": need finite s0, kappa > 0, c_eps >= 0, delta > 0");
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" dg_status dg_hex_av_viscosity(dg_hex_mesh h, const dg_params* prm, const dg_av_params* av, const double* q,
+                                         double* s_out, double* eps_out, double* G_out, hipStream_t stream) {
+  if (!h) return fail(DG_ERR_ARG, "dg_hex_av_viscosity: null mesh");
+  dg_status st = check_euler_params("dg_hex_av_viscosity", prm);
+  if (st == DG_OK) st = check_av("dg_hex_av_viscosity", av);
+  if (st != DG_OK) return st;
+  if (!q || !G_out || !eps_out || !aligned8(q) || !aligned8(G_out) || !aligned8(eps_out) || (s_out && !aligned8(s_out)))
+    return fail(DG_ERR_ARG, "dg_hex_av_viscosity: null or misaligned pointer");
+  const HexMesh& m = *reinterpret_cast<const HexMesh*>(h);
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_av_viscosity: hipSetDevice failed");
+  return launch_hex_av_flux(m, *av, prm->gamma, q, G_out, s_out, eps_out, stream);
+}
+
+extern "C" dg_status dg_hex_av_rhs(dg_hex_mesh h, const dg_params* prm, const dg_av_params* av, const double* q,
+                                   double* rhs, double* work, hipStream_t stream) {
+  if (!h) return fail(DG_ERR_ARG, "dg_hex_av_rhs: null mesh");
+  dg_status st = check_euler_params("dg_hex_av_rhs", prm);
+  if (st == DG_OK) st = check_av("dg_hex_av_rhs", av);
+  if (st != DG_OK) return st;
+  if (!q || !rhs || !work || !aligned8(q) || !aligned8(rhs) || !aligned8(work))
+    return fail(DG_ERR_ARG, "dg_hex_av_rhs: null or misaligned pointer");
+  const HexMesh& m = *reinterpret_cast<const HexMesh*>(h);
+  const size_t n = static_cast<size_t>(5) * m.E * m.Np;
+  const size_t nw = 3 * n + 2 * static_cast<size_t>(m.E);
+  if ((rhs < q + n && q < rhs + n) || (work < q + n && q < work + nw) || (work < rhs + n && rhs < work + nw))
+    return fail(DG_ERR_ARG, "dg_hex_av_rhs: q, rhs and work must not overlap");
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_av_rhs: hipSetDevice failed");
+  double* G = work;
+  st = launch_hex_av_flux(m, *av, prm->gamma, q, G, work + 3 * n, work + 3 * n + m.E, stream);
+  if (st != DG_OK) return st;
+  return launch_rhs_hex_av(m, prm->gamma, q, G, work + 3 * n + m.E, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+}
+
+extern "C" dg_status dg_hex_limit(dg_hex_mesh h, const dg_params* prm, const dg_av_params* av, double* q,
+                                  hipStream_t stream) {
+  if (!h) return fail(DG_ERR_ARG, "dg_hex_limit: null mesh");
+  dg_status st = check_euler_params("dg_hex_limit", prm);
+  if (st == DG_OK) st = check_av("dg_hex_limit", av);
+  if (st != DG_OK) return st;
+  if (!q || !aligned8(q)) return fail(DG_ERR_ARG, "dg_hex_limit: null or misaligned q");
+  const HexMesh& m = *reinterpret_cast<const HexMesh*>(h);
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_limit: hipSetDevice failed");
+  return launch_hex_limit(m, *av, prm->gamma, q, stream);
+}
+
+extern "C" dg_status dg_hex_shock_rk_step(dg_hex_mesh h, const dg_params* prm, const dg_av_params* av, double* q,
+                                          double* work, double t, double dt, hipStream_t stream) {
+  (void)t;
+  if (!h) return fail(DG_ERR_ARG, "dg_hex_shock_rk_step: null mesh");
+  dg_status st = check_euler_params("dg_hex_shock_rk_step", prm);
+  if (st == DG_OK) st = check_av("dg_hex_shock_rk_step", av);
+  if (st != DG_OK) return st;
+  if (!std::isfinite(dt)) return fail(DG_ERR_ARG, "dg_hex_shock_rk_step: dt must be finite");
+  if (!q || !work || !aligned8(q) || !aligned8(work))
+    return fail(DG_ERR_ARG, "dg_hex_shock_rk_step: null or misaligned pointer");
+  const HexMesh& m = *reinterpret_cast<const HexMesh*>(h);
+  const size_t n = static_cast<size_t>(5) * m.E * m.Np;
+  const size_t nw = 5 * n + 2 * static_cast<size_t>(m.E);
+  if (work < q + n && q < work + nw) return fail(DG_ERR_ARG, "dg_hex_shock_rk_step: work overlaps q");
+  DeviceGuard g(m.device);
+  if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_shock_rk_step: hipSetDevice failed");
+  // work = [res | second state | G (3 n) | s (E) | eps (E)]; each stage: the
+  // viscous fluxes of its input, the fused RHS + stage update into the other
+  // buffer, the limiter on that new stage state
+  double* res = work;
+  double* buf[2] = {q, work + n};
+  double* G = work + 2 * n;
+  for (int s = 0; s < 5; ++s) {
+    const double* qin = buf[s & 1];
+    double* qout = buf[(s + 1) & 1];
+    st = launch_hex_av_flux(m, *av, prm->gamma, qin, G, work + 5 * n, work + 5 * n + m.E, stream);
+    if (st == DG_OK)
+      st = launch_rhs_hex_av(m, prm->gamma, qin, G, work + 5 * n + m.E, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt,
+                             true, stream);
+    if (st == DG_OK) st = launch_hex_limit(m, *av, prm->gamma, qout, stream);
+    if (st != DG_OK) return st;
+  }
+  DG_HIP(hipMemcpyAsync(q, buf[1], n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  return DG_OK;
 }

@@ -12,7 +12,22 @@ from . import dg
 # every symbol include/dg_hex.h declares
 EXPORTS = ("dg_hex_reference_operators", "dg_hex_mesh_create", "dg_hex_mesh_info", "dg_hex_mesh_nodes",
            "dg_hex_mesh_destroy", "dg_hex_rhs", "dg_hex_rk_step", "dg_hex_oi_operators", "dg_hex_rhs_oi",
-           "dg_hex_rk_step_oi")
+           "dg_hex_rk_step_oi", "dg_hex_av_viscosity", "dg_hex_av_rhs", "dg_hex_limit", "dg_hex_shock_rk_step")
+
+AV_RHS_WORK = 15     # doubles per node of dg_hex_av_rhs scratch (plus 2 per element)
+SHOCK_STEP_WORK = 25  # doubles per node of dg_hex_shock_rk_step scratch (plus 2 per element)
+
+
+class AvParams(ctypes.Structure):
+    _fields_ = [("s0", ctypes.c_double), ("kappa", ctypes.c_double), ("c_eps", ctypes.c_double),
+                ("delta", ctypes.c_double)]
+
+
+def av_params(order: int, s0=None, kappa: float = 1.0, c_eps: float = 0.5, delta: float = 1e-10) -> AvParams:
+    """Shock-capturing parameters; s0 defaults to -(1 + 4 log10 p)."""
+    import math
+    return AvParams(-(1.0 + 4.0 * math.log10(order)) if s0 is None else float(s0), float(kappa), float(c_eps),
+                    float(delta))
 
 _c_p = ctypes.c_void_p
 _dbl = ctypes.c_double
@@ -35,6 +50,11 @@ def lib():
         L.dg_hex_oi_operators.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_p, _c_p, _c_p]
         L.dg_hex_rhs_oi.argtypes = [_c_p, ctypes.POINTER(dg._Params), _c_p, _c_p, _c_p]
         L.dg_hex_rk_step_oi.argtypes = [_c_p, ctypes.POINTER(dg._Params), _c_p, _c_p, _dbl, _dbl, _c_p]
+        P_, A_ = ctypes.POINTER(dg._Params), ctypes.POINTER(AvParams)
+        L.dg_hex_av_viscosity.argtypes = [_c_p, P_, A_, _c_p, _c_p, _c_p, _c_p, _c_p]
+        L.dg_hex_av_rhs.argtypes = [_c_p, P_, A_, _c_p, _c_p, _c_p, _c_p]
+        L.dg_hex_limit.argtypes = [_c_p, P_, A_, _c_p, _c_p]
+        L.dg_hex_shock_rk_step.argtypes = [_c_p, P_, A_, _c_p, _c_p, _dbl, _dbl, _c_p]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int
         _done = True
@@ -128,4 +148,59 @@ def rk_step(mesh: HexMesh, q, work, t: float, dt: float, gamma: float = 1.4, ove
     fn = lib().dg_hex_rk_step_oi if overintegrate else lib().dg_hex_rk_step
     dg._check(fn(mesh.handle, ctypes.byref(prm), dg._dev_ptr(q), dg._dev_ptr(work), float(t), float(dt),
                  dg._stream(stream)))
+    return q
+
+
+def _optr(t, dtype="float64"):
+    return dg._dev_ptr(t, dtype) if t is not None else ctypes.c_void_p()
+
+
+def av_viscosity(mesh: HexMesh, q, G, s_out, eps_out, av: AvParams = None, gamma: float = 1.4, stream=None):
+    """Indicator s (optional) and viscosity eps per element ([E]) and the
+    viscous fluxes G [3, 5, E, Np] of q (written only where eps > 0)."""
+    dg._check_state(mesh, q, 5, "q")
+    if G.numel() != 15 * mesh.E * mesh.Np:
+        raise ValueError("G must hold 3 x 5 x E x Np doubles")
+    for t in (s_out, eps_out):
+        if t is not None and t.numel() != mesh.E:
+            raise ValueError("s_out / eps_out must hold E doubles")
+    if eps_out is None:
+        raise ValueError("eps_out is required")
+    av = av_params(mesh.order) if av is None else av
+    prm = dg._params(gamma)
+    dg._check(lib().dg_hex_av_viscosity(mesh.handle, ctypes.byref(prm), ctypes.byref(av), dg._dev_ptr(q),
+                                        _optr(s_out), _optr(eps_out), dg._dev_ptr(G), dg._stream(stream)))
+
+
+def av_rhs(mesh: HexMesh, q, out, work, av: AvParams = None, gamma: float = 1.4, stream=None):
+    """out <- Euler RHS + artificial-viscosity term of q."""
+    dg._check_state(mesh, q, 5, "q")
+    dg._check_state(mesh, out, 5, "out")
+    if work.numel() < AV_RHS_WORK * mesh.E * mesh.Np + 2 * mesh.E:
+        raise ValueError("work must hold >= 15 E Np + 2 E doubles")
+    av = av_params(mesh.order) if av is None else av
+    prm = dg._params(gamma)
+    dg._check(lib().dg_hex_av_rhs(mesh.handle, ctypes.byref(prm), ctypes.byref(av), dg._dev_ptr(q), dg._dev_ptr(out),
+                                  dg._dev_ptr(work), dg._stream(stream)))
+    return out
+
+
+def limit(mesh: HexMesh, q, av: AvParams = None, gamma: float = 1.4, stream=None):
+    """Positivity limiter of q in place."""
+    dg._check_state(mesh, q, 5, "q")
+    av = av_params(mesh.order) if av is None else av
+    prm = dg._params(gamma)
+    dg._check(lib().dg_hex_limit(mesh.handle, ctypes.byref(prm), ctypes.byref(av), dg._dev_ptr(q), dg._stream(stream)))
+    return q
+
+
+def shock_rk_step(mesh: HexMesh, q, work, t: float, dt: float, av: AvParams = None, gamma: float = 1.4, stream=None):
+    """One LSRK(5,4) step with artificial viscosity and the limiter on every stage."""
+    dg._check_state(mesh, q, 5, "q")
+    if work.numel() < SHOCK_STEP_WORK * mesh.E * mesh.Np + 2 * mesh.E:
+        raise ValueError("work must hold >= 25 E Np + 2 E doubles")
+    av = av_params(mesh.order) if av is None else av
+    prm = dg._params(gamma)
+    dg._check(lib().dg_hex_shock_rk_step(mesh.handle, ctypes.byref(prm), ctypes.byref(av), dg._dev_ptr(q),
+                                         dg._dev_ptr(work), float(t), float(dt), dg._stream(stream)))
     return q
