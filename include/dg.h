@@ -144,10 +144,11 @@ dg_status dg_rhs(dg_mesh m, const dg_params* prm, dg_precision prec, const doubl
  * and from the previous stage's values after it (as dg_ns_rk_step).  A
  * non-finite new state raises the device's non-finite flag.  t is accepted for non-autonomous models (the Euler RHS does
  * not depend on it).  With the mesh's launch configuration for prec (below)
- * each stage is one fused launch (RHS + stage update into a second state
- * buffer, then a final copy returns the state to q) or an RHS launch into
- * work followed by the pointwise update of q in place; both give the same
- * bits. */
+ * each stage is one fused launch (RHS + stage update into another state
+ * buffer: the intermediate states and the residual rotate through q and
+ * the two halves of work so that the fifth stage writes q, with no copy)
+ * or an RHS launch into work followed by the pointwise update of q in
+ * place; both give the same bits. */
 dg_status dg_rk_step(dg_mesh m, const dg_params* prm, dg_precision prec, double* q, double* work,
                      double t, double dt, hipStream_t stream);
 
@@ -155,7 +156,7 @@ dg_status dg_rk_step(dg_mesh m, const dg_params* prm, dg_precision prec, double*
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * Euler step as dg_rk_step (model 0, any contraction precision, the mesh's
  * launch configuration, the same kernels and so the same bits), with the
- * residual and the second state buffer in a fixed array the library holds
+ * two state-sized work buffers in a fixed array the library holds
  * on each GPU instead of a caller workspace.  It calls no allocator.
  *  - Limit: the state may hold at most DG_NOALLOC_MAX_STATE doubles
  *    (5 E Np <= 8,388,608: up to 83,886 tets at p = 3, e.g. one GPU's
@@ -334,7 +335,8 @@ dg_status dg_ns_rhs(dg_mesh m, const dg_params* prm, const double* q, const doub
  * pass, right-hand side fused with the stage update.  q (device
  * [12][E][Np]) is updated in place; T (device [E][Np]) is the first stage's
  * Newton start and returns the temperatures of the last stage's input.
- * work: device scratch of 58 E Np doubles (residual, second state buffer,
+ * work: device scratch of 58 E Np doubles (two state-sized buffers that the
+ * residual and the intermediate states rotate through, as in dg_rk_step;
  * gradients; the last E Np doubles hold the last stage's int32 Newton
  * iteration counts, -1 where it did not converge). */
 dg_status dg_ns_rk_step(dg_mesh m, const dg_params* prm, double* q, double* T, double* work, double dt, double tol,

@@ -62,6 +62,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2))) v
     LowArgs A;
     A.q = odd ? M.tmp : M.q;
     A.qout = odd ? M.q : M.tmp;
+    A.res_in = M.res;
     A.res = M.res;
     A.rhs = nullptr;
     A.geo = M.geo;
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P < 4 ? 3 :
   LowArgs A;
   A.q = odd ? M.tmp : M.q;
   A.qout = odd ? M.q : M.tmp;
+  A.res_in = M.res;
   A.res = M.res;
   A.rhs = nullptr;
   A.geo = M.geo;

@@ -28,8 +28,8 @@ const double kLsrkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 1
                           1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                           2277821191437.0 / 14882151754819.0};
 
-// One LSRK(5,4) Euler step of q in place with work = [residual | second
-// state buffer] (2 n doubles); the device is current.  Allocates nothing.
+// One LSRK(5,4) Euler step of q in place with work = two state-sized
+// buffers (2 n doubles); the device is current.  Allocates nothing.
 dg_status rk_step_euler(const Mesh& m, double gamma, dg_precision prec, double* q, double* work, double dt,
                         hipStream_t stream) {
   const size_t n = static_cast<size_t>(5) * m.E * m.Np;
@@ -40,25 +40,22 @@ dg_status rk_step_euler(const Mesh& m, double gamma, dg_precision prec, double* 
     double* rhs = work + n;
     for (int s = 0; s < 5; ++s) {
       st = prec == DG_FP64
-               ? launch_rhs_euler_fp64(m, gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream)
-               : launch_rhs_euler_lowp(m, prec, gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+               ? launch_rhs_euler_fp64(m, gamma, q, rhs, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream)
+               : launch_rhs_euler_lowp(m, prec, gamma, q, rhs, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
       if (st != DG_OK) return st;
       st = launch_lsrk_update(static_cast<int64_t>(n), kLsrkA[s], kLsrkB[s], dt, rhs, res, q, stream);
       if (st != DG_OK) return st;
     }
     return DG_OK;
   }
-  double* buf[2] = {q, work + n};
   for (int s = 0; s < 5; ++s) {
-    const double* qin = buf[s & 1];
-    double* qout = buf[(s + 1) & 1];
-    st = prec == DG_FP64
-             ? launch_rhs_euler_fp64(m, gamma, qin, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt, true, stream)
-             : launch_rhs_euler_lowp(m, prec, gamma, qin, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt, true, stream);
+    const LsrkBuffers B = lsrk_buffers(s, q, work, work + n);
+    st = prec == DG_FP64 ? launch_rhs_euler_fp64(m, gamma, B.q_in, nullptr, B.res_in, B.res_out, B.q_out, kLsrkA[s],
+                                                 kLsrkB[s], dt, true, stream)
+                         : launch_rhs_euler_lowp(m, prec, gamma, B.q_in, nullptr, B.res_in, B.res_out, B.q_out,
+                                                 kLsrkA[s], kLsrkB[s], dt, true, stream);
     if (st != DG_OK) return st;
   }
-  // five stages leave the state in the second buffer
-  DG_HIP(hipMemcpyAsync(q, buf[1], n * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return DG_OK;
 }
 
@@ -118,8 +115,8 @@ extern "C" dg_status dg_rhs(dg_mesh h, const dg_params* prm, dg_precision prec, 
   if (q == rhs || (rhs < q + n && q < rhs + n)) return fail(DG_ERR_ARG, "dg_rhs: q and rhs overlap");
   DeviceGuard g(m.device);
   if (!g.ok) return fail(DG_ERR_HIP, "dg_rhs: hipSetDevice failed");
-  if (prec == DG_FP64) return launch_rhs_euler_fp64(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
-  return launch_rhs_euler_lowp(m, prec, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+  if (prec == DG_FP64) return launch_rhs_euler_fp64(m, prm->gamma, q, rhs, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+  return launch_rhs_euler_lowp(m, prec, prm->gamma, q, rhs, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
 }
 
 extern "C" dg_status dg_rk_step(dg_mesh h, const dg_params* prm, dg_precision prec, double* q, double* work,

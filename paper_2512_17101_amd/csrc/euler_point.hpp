@@ -203,12 +203,15 @@ __device__ inline void stage_tile_dma(double* sq, const double* __restrict__ q, 
 // One entry of the fused 2N-storage Runge-Kutta stage
 //   res <- a res + dt rhs;  q_out <- q + b res
 // from values of res and q loaded beforehand (res_old is not used when
-// a == 0: the first stage's residual buffer may hold anything).
-__device__ inline double stage_store(int64_t idx, double val, double res_old, double q_old, double* __restrict__ res,
-                                     double* __restrict__ qout, double a, double b, double dt) {
+// a == 0: the first stage's residual buffer may hold anything).  The new
+// residual goes to res (skipped when res is null: the last stage's is not
+// needed); res and qout may be the buffer the old residual came from,
+// since every entry is read before it is written by the same thread.
+__device__ inline double stage_store(int64_t idx, double val, double res_old, double q_old, double* res, double* qout,
+                                     double a, double b, double dt) {
   const double r = (a == 0.0 ? 0.0 : a * res_old) + dt * val;
   const double qn = q_old + b * r;
-  res[idx] = r;
+  if (res) res[idx] = r;
   qout[idx] = qn;
   return qn;
 }
@@ -224,7 +227,7 @@ __device__ inline double stage_store(int64_t idx, double val, double res_old, do
 // the new state of a fused stage) raises the device's non-finite flag.
 template <bool FUSED, int TQ>
 __device__ inline void store_tile(const double* sq, int nval, int64_t base, int64_t Es, int lane,
-                                  double* __restrict__ rhs, double* __restrict__ res, double* __restrict__ qout,
+                                  double* __restrict__ rhs, const double* res_in, double* res, double* qout,
                                   const double* __restrict__ q, double a, double b, double dt, unsigned* flags) {
   constexpr int KN = (TQ + 63) / 64;
   constexpr int FG = tile_round_fields<TQ>();
@@ -260,7 +263,7 @@ __device__ inline void store_tile(const double* sq, int nval, int64_t base, int6
           const int i = 64 * k + lane;
           const bool ok = f0 + ff < 5;  // known at compile time
           const int64_t idx = (f0 + ff) * Es + base + (i < nval ? i : nval - 1);  // clamped: unconditional loads
-          rv[ff][k] = ok && a != 0.0 ? res[idx] : 0.0;
+          rv[ff][k] = ok && a != 0.0 ? res_in[idx] : 0.0;
           qv[ff][k] = ok ? q[idx] : 0.0;
         }
 #pragma unroll

@@ -48,8 +48,9 @@ struct HexArgs {
   const double* __restrict__ G;   // artificial viscosity: viscous fluxes [3][5][E][Np], valid where eps > 0
   const double* __restrict__ eps; // artificial viscosity per element
   double* __restrict__ rhs;
-  double* __restrict__ res;
-  double* __restrict__ qout;
+  const double* res_in;  // may alias res or qout (entry-wise)
+  double* res;           // null: the new residual is not stored
+  double* qout;
   const double* __restrict__ ih;  // [nx | ny | nz] 2 / h
   const double* __restrict__ op;  // [D1 | lift]
   int nx, ny, nz;
@@ -179,11 +180,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
   const double q0 = qv[0], q1 = qv[1], q2 = qv[2], q3 = qv[3], q4 = qv[4];
   double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0, r4 = 0.0;
   if (FUSED && A.a != 0.0) {
-    r0 = A.res[idx];
-    r1 = A.res[Es + idx];
-    r2 = A.res[2 * Es + idx];
-    r3 = A.res[3 * Es + idx];
-    r4 = A.res[4 * Es + idx];
+    r0 = A.res_in[idx];
+    r1 = A.res_in[Es + idx];
+    r2 = A.res_in[2 * Es + idx];
+    r3 = A.res_in[3 * Es + idx];
+    r4 = A.res_in[4 * Es + idx];
   }
   const int cx = e % A.nx, cxy = e / A.nx;
   const double ihx = A.ih[cx], ihy = A.ih[A.nx + cxy % A.ny], ihz = A.ih[A.nx + A.ny + cxy / A.ny];
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
         const double ro = f == 0 ? r0 : f == 1 ? r1 : f == 2 ? r2 : f == 3 ? r3 : r4;
         const double r = (A.a == 0.0 ? 0.0 : A.a * ro) + A.dt * out;
         const double qn = qf + A.b * r;
-        A.res[f * Es + idx] = r;
+        if (A.res) A.res[f * Es + idx] = r;
         A.qout[f * Es + idx] = qn;
         bad |= nonfinite(qn);
       } else {
@@ -263,19 +264,20 @@ dg_status launch_p(const HexMesh& m, const HexArgs& A, bool fused, hipStream_t s
 
 }  // namespace
 
-dg_status launch_rhs_hex(const HexMesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
-                         double a, double b, double dt, bool fused, hipStream_t s) {
-  return launch_rhs_hex_av(m, gamma, q, nullptr, nullptr, rhs, res, q_out, a, b, dt, fused, s);
+dg_status launch_rhs_hex(const HexMesh& m, double gamma, const double* q, double* rhs, const double* res_in,
+                         double* res, double* q_out, double a, double b, double dt, bool fused, hipStream_t s) {
+  return launch_rhs_hex_av(m, gamma, q, nullptr, nullptr, rhs, res_in, res, q_out, a, b, dt, fused, s);
 }
 
 dg_status launch_rhs_hex_av(const HexMesh& m, double gamma, const double* q, const double* G, const double* eps,
-                            double* rhs, double* res, double* q_out, double a, double b, double dt, bool fused,
-                            hipStream_t s) {
+                            double* rhs, const double* res_in, double* res, double* q_out, double a, double b,
+                            double dt, bool fused, hipStream_t s) {
   HexArgs A;
   A.q = q;
   A.G = G;
   A.eps = eps;
   A.rhs = rhs;
+  A.res_in = res_in;
   A.res = res;
   A.qout = q_out;
   A.ih = m.d_ih;

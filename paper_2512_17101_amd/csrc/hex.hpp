@@ -41,8 +41,9 @@ bool build_hex_oi(int p, std::vector<double>& xq, std::vector<double>& wq, std::
 
 // Overintegrated RHS (weak form, fluxes at the Gauss points), optionally
 // through the fused stage update as below.
-dg_status launch_rhs_hex_oi(const HexMesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
-                            double a, double b, double dt, bool fused_lsrk, hipStream_t s);
+dg_status launch_rhs_hex_oi(const HexMesh& m, double gamma, const double* q, double* rhs, const double* res_in,
+                            double* res, double* q_out, double a, double b, double dt, bool fused_lsrk,
+                            hipStream_t s);
 
 // Shock-capturing tables of order p: the inverse orthonormal Legendre
 // Vandermonde on the LGL points (row-major) and the weights int l_i.
@@ -58,12 +59,14 @@ dg_status launch_hex_limit(const HexMesh& m, const dg_av_params& av, double gamm
 // G is read only in elements with eps > 0, elsewhere it is zero), optionally
 // through the fused stage update.
 dg_status launch_rhs_hex_av(const HexMesh& m, double gamma, const double* q, const double* G, const double* eps,
-                            double* rhs, double* res, double* q_out, double a, double b, double dt, bool fused_lsrk,
-                            hipStream_t s);
+                            double* rhs, const double* res_in, double* res, double* q_out, double a, double b,
+                            double dt, bool fused_lsrk, hipStream_t s);
 
 // RHS of q on the hex mesh; with fused_lsrk the result goes through the
-// stage update (res <- a res + dt rhs; q_out <- q + b res) instead of rhs.
-dg_status launch_rhs_hex(const HexMesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
-                         double a, double b, double dt, bool fused_lsrk, hipStream_t s);
+// stage update (res <- a res_in + dt rhs; q_out <- q + b res, res skipped
+// when null; res_in, res and q_out may share a buffer, as the stage reads
+// every entry before the same thread writes it) instead of rhs.
+dg_status launch_rhs_hex(const HexMesh& m, double gamma, const double* q, double* rhs, const double* res_in,
+                         double* res, double* q_out, double a, double b, double dt, bool fused_lsrk, hipStream_t s);
 
 }  // namespace dg

@@ -395,8 +395,8 @@ dg_status hex_rhs_form(dg_hex_mesh h, const dg_params* prm, const double* q, dou
   if (rhs < q + n && q < rhs + n) return fail(DG_ERR_ARG, std::string(who) + ": q and rhs overlap");
   DeviceGuard g(m.device);
   if (!g.ok) return fail(DG_ERR_HIP, std::string(who) + ": hipSetDevice failed");
-  return oi ? launch_rhs_hex_oi(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream)
-            : launch_rhs_hex(m, prm->gamma, q, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+  return oi ? launch_rhs_hex_oi(m, prm->gamma, q, rhs, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream)
+            : launch_rhs_hex(m, prm->gamma, q, rhs, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
 }
 
 dg_status hex_step_form(dg_hex_mesh h, const dg_params* prm, double* q, double* work, double dt, hipStream_t stream,
@@ -412,18 +412,17 @@ dg_status hex_step_form(dg_hex_mesh h, const dg_params* prm, double* q, double* 
   if (work < q + n && q < work + 2 * n) return fail(DG_ERR_ARG, std::string(who) + ": work overlaps q");
   DeviceGuard g(m.device);
   if (!g.ok) return fail(DG_ERR_HIP, std::string(who) + ": hipSetDevice failed");
-  // fused stages ping-pong between q and the second buffer (neighbouring
-  // elements still read the stage input); five stages end in the buffer
-  double* res = work;
-  double* buf[2] = {q, work + n};
+  // fused stages write another buffer than they read (neighbouring
+  // elements still read the stage input); q and the two halves of work
+  // rotate so that the fifth stage writes q
   for (int s = 0; s < 5; ++s) {
-    st = oi ? launch_rhs_hex_oi(m, prm->gamma, buf[s & 1], nullptr, res, buf[(s + 1) & 1], kLsrkA[s], kLsrkB[s], dt,
-                                true, stream)
-            : launch_rhs_hex(m, prm->gamma, buf[s & 1], nullptr, res, buf[(s + 1) & 1], kLsrkA[s], kLsrkB[s], dt, true,
-                             stream);
+    const LsrkBuffers B = lsrk_buffers(s, q, work, work + n);
+    st = oi ? launch_rhs_hex_oi(m, prm->gamma, B.q_in, nullptr, B.res_in, B.res_out, B.q_out, kLsrkA[s], kLsrkB[s],
+                                dt, true, stream)
+            : launch_rhs_hex(m, prm->gamma, B.q_in, nullptr, B.res_in, B.res_out, B.q_out, kLsrkA[s], kLsrkB[s], dt,
+                             true, stream);
     if (st != DG_OK) return st;
   }
-  DG_HIP(hipMemcpyAsync(q, buf[1], n * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return DG_OK;
 }
 
@@ -504,7 +503,7 @@ extern "C" dg_status dg_hex_av_rhs(dg_hex_mesh h, const dg_params* prm, const dg
   double* G = work;
   st = launch_hex_av_flux(m, *av, prm->gamma, q, G, work + 3 * n, work + 3 * n + m.E, stream);
   if (st != DG_OK) return st;
-  return launch_rhs_hex_av(m, prm->gamma, q, G, work + 3 * n + m.E, rhs, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
+  return launch_rhs_hex_av(m, prm->gamma, q, G, work + 3 * n + m.E, rhs, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, false, stream);
 }
 
 extern "C" dg_status dg_hex_limit(dg_hex_mesh h, const dg_params* prm, const dg_av_params* av, double* q,
@@ -536,22 +535,18 @@ extern "C" dg_status dg_hex_shock_rk_step(dg_hex_mesh h, const dg_params* prm, c
   if (work < q + n && q < work + nw) return fail(DG_ERR_ARG, "dg_hex_shock_rk_step: work overlaps q");
   DeviceGuard g(m.device);
   if (!g.ok) return fail(DG_ERR_HIP, "dg_hex_shock_rk_step: hipSetDevice failed");
-  // work = [res | second state | G (3 n) | s (E) | eps (E)]; each stage: the
-  // viscous fluxes of its input, the fused RHS + stage update into the other
-  // buffer, the limiter on that new stage state
-  double* res = work;
-  double* buf[2] = {q, work + n};
+  // work = [two state buffers | G (3 n) | s (E) | eps (E)]; each stage: the
+  // viscous fluxes of its input, the fused RHS + stage update into another
+  // buffer (rotating as in the plain step), the limiter on that new state
   double* G = work + 2 * n;
   for (int s = 0; s < 5; ++s) {
-    const double* qin = buf[s & 1];
-    double* qout = buf[(s + 1) & 1];
-    st = launch_hex_av_flux(m, *av, prm->gamma, qin, G, work + 5 * n, work + 5 * n + m.E, stream);
+    const LsrkBuffers B = lsrk_buffers(s, q, work, work + n);
+    st = launch_hex_av_flux(m, *av, prm->gamma, B.q_in, G, work + 5 * n, work + 5 * n + m.E, stream);
     if (st == DG_OK)
-      st = launch_rhs_hex_av(m, prm->gamma, qin, G, work + 5 * n + m.E, nullptr, res, qout, kLsrkA[s], kLsrkB[s], dt,
-                             true, stream);
-    if (st == DG_OK) st = launch_hex_limit(m, *av, prm->gamma, qout, stream);
+      st = launch_rhs_hex_av(m, prm->gamma, B.q_in, G, work + 5 * n + m.E, nullptr, B.res_in, B.res_out, B.q_out,
+                             kLsrkA[s], kLsrkB[s], dt, true, stream);
+    if (st == DG_OK) st = launch_hex_limit(m, *av, prm->gamma, B.q_out, stream);
     if (st != DG_OK) return st;
   }
-  DG_HIP(hipMemcpyAsync(q, buf[1], n * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return DG_OK;
 }

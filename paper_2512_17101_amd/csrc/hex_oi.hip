@@ -8,13 +8,24 @@
 //   rhs = sum_d (2 / h_d) [ (S along d, P along the others) F_d(quad)
 //                           - sum_side l_side x (P x P) Fhat_face(quad) ],
 //   S = M1^{-1} B'^T W,  P = M1^{-1} B^T W                         ((p+1) x nq).
-// At p = 4 this is about 220 kflop per element against 10 kB of state: the
-// FP64 pipe bounds it, not HBM.  Every contraction pass runs one line per
-// thread: the thread loads the line's inputs from LDS into registers and
-// forms all outputs of the line, the operator entries being compile-time
-// indices into a uniform table (scalar loads, not LDS traffic).  A block of
-// 256 threads owns max(1, 256 / nq^3) elements; the passes of a stage are
-// separated by barriers.
+// At p = 4 this is about 420 kflop per element against 10 kB of state: the
+// FP64 pipe bounds it, not HBM.
+//
+// One wave owns max(1, 64 / nq^2) elements (one at p = 3, 4; two at p = 2;
+// seven at p = 1) and is its own workgroup, so the passes are separated by
+// single-wave barriers.  Two kinds of pass:
+//  - line passes: a lane takes one line of an LDS array, loads its inputs
+//    into registers and forms every output of the line; the operator entries
+//    are compile-time indices into a uniform table (scalar loads);
+//  - column passes: a lane owns one (k1, k2) column of the element's quad
+//    grid (or one face quad point) and keeps its values in registers: the
+//    last interpolation pass, the fluxes and the first projection pass of
+//    the volume term, and the second face interpolation pass plus the
+//    Lax-Friedrichs flux, need no LDS round trip.
+// Faces come first (own and neighbour traces at the face quad points, the
+// flux there, its projection back to the face nodes, kept in LDS), then the
+// volume term field by field, to which each node adds the lifted face terms
+// of its line before the coalesced store (or the fused Runge-Kutta stage).
 #include "hex.hpp"
 
 namespace dg {
@@ -29,27 +40,38 @@ struct OiCfg {
   static constexpr int NQ = oi_nq(P);
   static constexpr int NP = N1 * N1 * N1;
   static constexpr int NF2 = N1 * N1;
-  static constexpr int Q3 = NQ * NQ * NQ;
-  static constexpr int EPB = Q3 >= 256 ? 1 : 256 / Q3;
+  static constexpr int QF = NQ * NQ;
+  static constexpr int EPW = QF >= 64 ? 1 : 64 / QF;  // elements per wave
+  // LDS row strides of arrays whose rows are one lane's line: odd, so that
+  // the lanes of a wave spread over the banks (an even stride of 8 doubles
+  // puts 16 lanes on one bank)
+  static constexpr int NQP = NQ | 1, N1P = N1 | 1;
   // offsets of the operator table [B (NQ x N1) | S (N1 x NQ) | P (N1 x NQ) | lift (N1 x 2)]
   static constexpr int OB = 0, OS = NQ * N1, OP = 2 * NQ * N1, OL = 3 * NQ * N1;
-  // LDS regions per element (doubles)
-  static constexpr int R_Q = 5 * NP;                                              // nodal state
-  static constexpr int R_OUT = 5 * NP;                                            // accumulated rhs
-  static constexpr int R_QQ = 5 * Q3;                                             // state at the quad points
-  static constexpr int R1 = cmax(cmax(5 * NF2 * NQ, 3 * NQ * NQ * N1), 10 * N1 * NQ + 5 * NQ * NQ);
-  static constexpr int R2 = cmax(cmax(5 * N1 * NQ * NQ, 3 * NQ * NF2), 2 * 5 * NQ * NQ);
-  static constexpr int R_F = cmax(3 * Q3, 30 * NF2 + 5 * NQ * N1);
-  static constexpr int PER_EL = R_Q + R_OUT + R_QQ + R1 + R2 + R_F;
-  static constexpr int KN = (EPB * 6 * 5 * NF2 + 255) / 256;  // neighbour face values per thread
-  static constexpr int KR = (EPB * 5 * NP + 255) / 256;       // output entries per thread
+  // LDS per element (doubles): own nodal state, the six face slices (the
+  // neighbour's nodes, then the projected face flux), scratch
+  static constexpr int L_Q = 5 * NP;
+  static constexpr int L_F = 6 * 5 * NF2;
+  // scratch layouts (row strides padded to NQP, N1P):
+  //   volume interpolation  W1 [NF2][NQP] at 0, W2 [N1][QF] at NF2 NQP
+  //   volume projection     Hs [N1][QF] at 0,   Gs [NF2][NQP] at N1 QF
+  //   faces                 T1 [2][5][N1][NQP], then Fh [5][NQ][NQP], at 0;
+  //                         U [5][NQ][N1P] at X_U
+  static constexpr int X_U = cmax(2 * 5 * N1 * NQP, 5 * NQ * NQP);
+  static constexpr int L_S = cmax(NF2 * NQP + N1 * QF, X_U + 5 * NQ * N1P);
+  static constexpr int PER_EL = L_Q + L_F + L_S;
+  static constexpr int KQ = (EPW * 5 * NP + 63) / 64;       // own state loads per lane
+  static constexpr int KN = (EPW * 6 * 5 * NF2 + 63) / 64;  // neighbour face loads per lane
+  static_assert(EPW * QF <= 64, "one column per lane");
+  static_assert(EPW * NF2 <= 64, "one output line per lane");
 };
 
 struct OiArgs {
   const double* __restrict__ q;
   double* __restrict__ rhs;
-  double* __restrict__ res;
-  double* __restrict__ qout;
+  const double* res_in;  // may alias res or qout (entry-wise)
+  double* res;           // null: the new residual is not stored
+  double* qout;
   const double* __restrict__ ih;  // [nx | ny | nz] 2 / h
   const double* __restrict__ op;  // [B | S | P | lift]
   int nx, ny, nz;
@@ -58,15 +80,32 @@ struct OiArgs {
   unsigned* flags;
 };
 
+typedef const __attribute__((address_space(4))) double cdouble;
+// The operator entries of one output of a line, read through the constant
+// address space at an offset the compiler cannot see through: scalar loads
+// issued at each use.  With plain loads the compiler hoisted every table
+// entry out of the loops (about 130 doubles at p = 4), overflowed the
+// scalar registers, spilled them to vector-register lanes (some 1,500
+// v_readlane / v_writelane per wave) and ran out of vector registers.
+// At p = 1 (2 x 3 operators, 22 table entries in all) the hoisted values fit
+// and the plain loads are faster.
+template <int NO, int NI>
+__device__ inline cdouble* op_at(const double* A) {
+  int z = 0;
+  if constexpr (NO * NI > 8) asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return (cdouble*)(reinterpret_cast<uintptr_t>(A)) + __builtin_amdgcn_readfirstlane(z);
+}
+
 // out[o * so] = sum_i A[o * NI + i] in[i * si]: one line, operator entries at
 // compile-time offsets of a uniform table
 template <int NO, int NI>
-__device__ inline void line(const double* __restrict__ A, const double* in, int si, double* out, int so) {
+__device__ inline void line(const double* __restrict__ A0, const double* in, int si, double* out, int so) {
   double x[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) x[i] = in[i * si];
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
+    cdouble* A = op_at<NO, NI>(A0);
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < NI; ++i) s = fma(A[o * NI + i], x[i], s);
@@ -74,248 +113,311 @@ __device__ inline void line(const double* __restrict__ A, const double* in, int 
   }
 }
 
-// primitive velocities and pressure of a conserved state
-__device__ inline void prim(const double q[5], double g, double& u, double& v, double& w, double& p) {
-  const double ir = 1.0 / q[0];
-  u = q[1] * ir;
-  v = q[2] * ir;
-  w = q[3] * ir;
-  p = (g - 1.0) * (q[4] - 0.5 * (q[1] * u + q[2] * v + q[3] * w));
+// the same, with the line's inputs already in registers
+template <int NO, int NI>
+__device__ inline void line_r(const double* __restrict__ A0, const double (&x)[NI], double (&out)[NO]) {
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    cdouble* A = op_at<NO, NI>(A0);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) s = fma(A[o * NI + i], x[i], s);
+    out[o] = s;
+  }
 }
 
+// the element across face (d, side) of element e on the periodic grid
+__device__ inline int face_neighbour(int e, int d, int side, int nx, int ny, int nz) {
+  const int cx = e % nx, cxy = e / nx, cy = cxy % ny, cz = cxy / ny;
+  const int cd = d == 0 ? cx : d == 1 ? cy : cz;
+  const int nd = d == 0 ? nx : d == 1 ? ny : nz;
+  const int stride = d == 0 ? 1 : d == 1 ? nx : nx * ny;
+  return side ? (cd == nd - 1 ? e - (nd - 1) * stride : e + stride) : (cd == 0 ? e + (nd - 1) * stride : e - stride);
+}
+
+// the volume node at face coordinates (i1 fast, i2 slow) of face d, fixed
+// coordinate fo along d
+template <int N1>
+__device__ inline int face_node(int d, int fo, int i1, int i2) {
+  return d == 0 ? fo + N1 * (i1 + N1 * i2) : d == 1 ? i1 + N1 * (fo + N1 * i2) : i1 + N1 * (i2 + N1 * fo);
+}
+
+// Registers: the column state (six values at nq points) plus one line's
+// operands; about 185-200 at p = 4 (two waves per SIMD, where the 16 kB of
+// LDS per element would allow 2.5), 140-155 at p = 3.
 template <int P, bool FUSED>
-__global__ __launch_bounds__(256) void hex_oi_kernel(OiArgs A) {
+__global__ __launch_bounds__(64) void hex_oi_kernel(OiArgs A) {
   using C = OiCfg<P>;
-  constexpr int N1 = C::N1, NQ = C::NQ, NP = C::NP, NF2 = C::NF2, Q3 = C::Q3, EPB = C::EPB;
-  __shared__ double s_mem[EPB * C::PER_EL];
-  double* sQ = s_mem;
-  double* sOut = sQ + EPB * C::R_Q;
-  double* sQQ = sOut + EPB * C::R_OUT;
-  double* sR1 = sQQ + EPB * C::R_QQ;
-  double* sR2 = sR1 + EPB * C::R1;
-  double* sF = sR2 + EPB * C::R2;
-  const int tid = threadIdx.x;
+  constexpr int N1 = C::N1, NQ = C::NQ, NP = C::NP, NF2 = C::NF2, QF = C::QF, EPW = C::EPW;
+  constexpr int NQP = C::NQP, N1P = C::N1P;
+  __shared__ double s_mem[EPW * C::PER_EL];
+  double* sQ = s_mem;                  // [EPW][5][NP]
+  double* sF = sQ + EPW * C::L_Q;      // [EPW][6][5][NF2]
+  double* sS = sF + EPW * C::L_F;      // [EPW][L_S]
+  const int lane = threadIdx.x;
   const int E = A.E;
-  const int e0 = blockIdx.x * EPB;
+  const int e0 = blockIdx.x * EPW;
   const size_t Es = static_cast<size_t>(E) * NP;
   const double* B = A.op + C::OB;
   const double* S = A.op + C::OS;
   const double* Pm = A.op + C::OP;
   const double* lift = A.op + C::OL;
+  const double g = A.gamma;
 
-  // (0) global reads: own state into LDS; neighbour face nodes and (fused)
-  // the residual into registers, written or used later
-  for (int t = tid; t < EPB * 5 * NP; t += 256) {
-    const int f = t / (EPB * NP), r = t - f * (EPB * NP);
-    const int el = r / NP, n = r - el * NP;
-    const int e = e0 + el < E ? e0 + el : E - 1;
-    sQ[(el * 5 + f) * NP + n] = A.q[f * Es + static_cast<size_t>(e) * NP + n];
-  }
-  double nb[C::KN];
+  // (0) own state (coalesced per field) and the neighbours' face nodes, all
+  // loads issued before the first LDS write
+  {
+    double qo[C::KQ], nb[C::KN];
 #pragma unroll
-  for (int u = 0; u < C::KN; ++u) {
-    const int t0 = tid + 256 * u;
-    const int t = t0 < EPB * 6 * 5 * NF2 ? t0 : EPB * 6 * 5 * NF2 - 1;
-    const int el = t / (6 * 5 * NF2), r = t - el * (6 * 5 * NF2);
-    const int face = r / (5 * NF2), r2 = r - face * (5 * NF2);
-    const int f = r2 / NF2, m = r2 - f * NF2;
-    const int d = face >> 1, side = face & 1;
-    const int ef = e0 + el < E ? e0 + el : E - 1;
-    const int cx = ef % A.nx, cxy = ef / A.nx, cy = cxy % A.ny, cz = cxy / A.ny;
-    const int cd = d == 0 ? cx : d == 1 ? cy : cz;
-    const int nd = d == 0 ? A.nx : d == 1 ? A.ny : A.nz;
-    const int stride = d == 0 ? 1 : d == 1 ? A.nx : A.nx * A.ny;
-    const int en = side ? (cd == nd - 1 ? ef - (nd - 1) * stride : ef + stride)
-                        : (cd == 0 ? ef + (nd - 1) * stride : ef - stride);
-    const int fast = m % N1, slow = m / N1, fn = side ? 0 : P;
-    const int nn = d == 0 ? fn + N1 * (fast + N1 * slow) : d == 1 ? fast + N1 * (fn + N1 * slow)
-                                                                   : fast + N1 * (slow + N1 * fn);
-    nb[u] = A.q[f * Es + static_cast<size_t>(en) * NP + nn];
-  }
-  double rv[C::KR];
-  if (FUSED) {
-#pragma unroll
-    for (int u = 0; u < C::KR; ++u) {
-      const int t0 = tid + 256 * u;
-      const int t = t0 < EPB * 5 * NP ? t0 : EPB * 5 * NP - 1;
-      const int f = t / (EPB * NP), r = t - f * (EPB * NP);
+    for (int u = 0; u < C::KQ; ++u) {
+      const int t0 = lane + 64 * u;
+      const int t = t0 < EPW * 5 * NP ? t0 : EPW * 5 * NP - 1;
+      const int f = t / (EPW * NP), r = t - f * (EPW * NP);
       const int el = r / NP, n = r - el * NP;
       const int e = e0 + el < E ? e0 + el : E - 1;
-      rv[u] = A.a == 0.0 ? 0.0 : A.res[f * Es + static_cast<size_t>(e) * NP + n];
+      qo[u] = A.q[f * Es + static_cast<size_t>(e) * NP + n];
     }
-  }
-  __syncthreads();
-
-  // (1) interpolation to the quad points: along a, b, c
-  for (int t = tid; t < EPB * 5 * NF2; t += 256)  // line (el, f, c, b)
-    line<NQ, N1>(B, sQ + t * N1, 1, sR1 + t * NQ, 1);
-  __syncthreads();
-  for (int t = tid; t < EPB * 5 * N1 * NQ; t += 256) {  // line (el, f, c, ka)
-    const int ef = t / (N1 * NQ), r = t - ef * (N1 * NQ), c = r / NQ, ka = r - c * NQ;
-    line<NQ, N1>(B, sR1 + ef * (NF2 * NQ) + c * N1 * NQ + ka, NQ, sR2 + ef * (N1 * NQ * NQ) + c * NQ * NQ + ka, NQ);
-  }
-  __syncthreads();
-  for (int t = tid; t < EPB * 5 * NQ * NQ; t += 256) {  // line (el, f, kb, ka)
-    const int ef = t / (NQ * NQ), r = t - ef * (NQ * NQ);
-    line<NQ, N1>(B, sR2 + ef * (N1 * NQ * NQ) + r, NQ * NQ, sQQ + ef * Q3 + r, NQ * NQ);
-  }
-  __syncthreads();
-
-  // (2) per field: the three fluxes at the quad points, then the projection
-  // (S along the flux's direction, P along the others), summed into sOut
-#pragma unroll 1
-  for (int f = 0; f < 5; ++f) {
-    for (int t = tid; t < EPB * Q3; t += 256) {
-      const int el = t / Q3, k = t - el * Q3;
-      double qq[5];
 #pragma unroll
-      for (int g = 0; g < 5; ++g) qq[g] = sQQ[(el * 5 + g) * Q3 + k];
-      double u, v, w, pr;
-      prim(qq, A.gamma, u, v, w, pr);
-      const double qe = f == 4 ? qq[4] + pr : (f == 0 ? qq[0] : f == 1 ? qq[1] : f == 2 ? qq[2] : qq[3]);
-      sF[(el * 3 + 0) * Q3 + k] = qe * u + (f == 1 ? pr : 0.0);
-      sF[(el * 3 + 1) * Q3 + k] = qe * v + (f == 2 ? pr : 0.0);
-      sF[(el * 3 + 2) * Q3 + k] = qe * w + (f == 3 ? pr : 0.0);
-    }
-    __syncthreads();
-    // along a: line (el, d, kc, kb), NQ -> N1
-    for (int t = tid; t < EPB * NQ * NQ; t += 256) {
-      const int el = t / (NQ * NQ), r = t - el * (NQ * NQ);
-      line<N1, NQ>(S, sF + (el * 3 + 0) * Q3 + r * NQ, 1, sR1 + (el * 3 + 0) * (NQ * NQ * N1) + r * N1, 1);
-      line<N1, NQ>(Pm, sF + (el * 3 + 1) * Q3 + r * NQ, 1, sR1 + (el * 3 + 1) * (NQ * NQ * N1) + r * N1, 1);
-      line<N1, NQ>(Pm, sF + (el * 3 + 2) * Q3 + r * NQ, 1, sR1 + (el * 3 + 2) * (NQ * NQ * N1) + r * N1, 1);
-    }
-    __syncthreads();
-    // along b: line (el, d, kc, a), NQ -> N1
-    for (int t = tid; t < EPB * NQ * N1; t += 256) {
-      const int el = t / (NQ * N1), r = t - el * (NQ * N1), kc = r / N1, a = r - kc * N1;
-      const int ib = kc * NQ * N1 + a, ob = kc * NF2 + a;
-      line<N1, NQ>(Pm, sR1 + (el * 3 + 0) * (NQ * NQ * N1) + ib, N1, sR2 + (el * 3 + 0) * (NQ * NF2) + ob, N1);
-      line<N1, NQ>(S, sR1 + (el * 3 + 1) * (NQ * NQ * N1) + ib, N1, sR2 + (el * 3 + 1) * (NQ * NF2) + ob, N1);
-      line<N1, NQ>(Pm, sR1 + (el * 3 + 2) * (NQ * NQ * N1) + ib, N1, sR2 + (el * 3 + 2) * (NQ * NF2) + ob, N1);
-    }
-    __syncthreads();
-    // along c and the sum over directions: line (el, b, a), NQ -> N1
-    for (int t = tid; t < EPB * NF2; t += 256) {
-      const int el = t / NF2, ba = t - el * NF2;
+    for (int u = 0; u < C::KN; ++u) {
+      const int t0 = lane + 64 * u;
+      const int t = t0 < EPW * 6 * 5 * NF2 ? t0 : EPW * 6 * 5 * NF2 - 1;
+      const int el = t / (6 * 5 * NF2), r = t - el * (6 * 5 * NF2);
+      const int face = r / (5 * NF2), r2 = r - face * (5 * NF2);
+      const int f = r2 / NF2, m = r2 - f * NF2;
+      const int d = face >> 1, side = face & 1;
       const int e = e0 + el < E ? e0 + el : E - 1;
-      const int cx = e % A.nx, cxy = e / A.nx;
-      const double ihx = A.ih[cx], ihy = A.ih[A.nx + cxy % A.ny], ihz = A.ih[A.nx + A.ny + cxy / A.ny];
-      double vx[N1], vy[N1], vz[N1];
-      line<N1, NQ>(Pm, sR2 + (el * 3 + 0) * (NQ * NF2) + ba, NF2, vx, 1);
-      line<N1, NQ>(Pm, sR2 + (el * 3 + 1) * (NQ * NF2) + ba, NF2, vy, 1);
-      line<N1, NQ>(S, sR2 + (el * 3 + 2) * (NQ * NF2) + ba, NF2, vz, 1);
-#pragma unroll
-      for (int c = 0; c < N1; ++c) sOut[(el * 5 + f) * NP + c * NF2 + ba] = ihx * vx[c] + ihy * vy[c] + ihz * vz[c];
+      const int en = face_neighbour(e, d, side, A.nx, A.ny, A.nz);
+      nb[u] = A.q[f * Es + static_cast<size_t>(en) * NP + face_node<N1>(d, side ? 0 : P, m % N1, m / N1)];
     }
-    __syncthreads();
-  }
-
-  // (3) faces: the neighbour face nodes into LDS (the flux region is free now)
 #pragma unroll
-  for (int u = 0; u < C::KN; ++u) {
-    const int t = tid + 256 * u;
-    if (t < EPB * 6 * 5 * NF2) sF[t] = nb[u];
+    for (int u = 0; u < C::KQ; ++u) {
+      const int t = lane + 64 * u;
+      if (t < EPW * 5 * NP) {
+        const int f = t / (EPW * NP), r = t - f * (EPW * NP);
+        const int el = r / NP, n = r - el * NP;
+        sQ[(el * 5 + f) * NP + n] = qo[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < C::KN; ++u) {
+      const int t = lane + 64 * u;
+      if (t < EPW * 6 * 5 * NF2) sF[t] = nb[u];
+    }
   }
   __syncthreads();
+
+  // column-pass identity of this lane: element cel, quad column / face point
+  // ck = k2 NQ + k1 (idle lanes read in-bounds scratch and write nothing)
+  const bool col = lane < EPW * QF;
+  const int cel = col ? lane / QF : 0;
+  const int ck = lane - cel * QF;
+  const int ck2 = col ? ck / NQ : 0;
+  const int ck1 = ck - ck2 * NQ;
+  double* cS = sS + cel * C::L_S;
+
+  // (1) faces: Fhat at the face quad points, projected back to the face
+  // nodes with P x P, stored over that face's neighbour slice
+  {
+    double Brow[N1];  // row k2 of B, for this lane's face point
+#pragma unroll
+    for (int i = 0; i < N1; ++i) Brow[i] = B[ck2 * N1 + i];
 #pragma unroll 1
-  for (int face = 0; face < 6; ++face) {
-    const int d = face >> 1, side = face & 1;
-    const int fo = side ? P : 0;
-    // interpolation along the face's fast axis: line (el, s2, f, slow), own (s2 = 0) and neighbour (1)
-    for (int t = tid; t < EPB * 2 * 5 * N1; t += 256) {
-      const int el = t / (10 * N1), r = t - el * (10 * N1), s2 = r / (5 * N1), r2 = r - s2 * (5 * N1);
-      const int f = r2 / N1, slow = r2 - f * N1;
-      double* out = sR1 + ((el * 2 + s2) * 5 + f) * (N1 * NQ) + slow * NQ;
-      if (s2 == 0) {
-        const double* qe = sQ + (el * 5 + f) * NP;
-        if (d == 0) line<NQ, N1>(B, qe + fo + N1 * N1 * slow, N1, out, 1);
-        else if (d == 1) line<NQ, N1>(B, qe + N1 * fo + NF2 * slow, 1, out, 1);
-        else line<NQ, N1>(B, qe + N1 * slow + NF2 * fo, 1, out, 1);
-      } else {
-        line<NQ, N1>(B, sF + ((el * 6 + face) * 5 + f) * NF2 + slow * N1, 1, out, 1);
+    for (int face = 0; face < 6; ++face) {
+      const int d = face >> 1, side = face & 1;
+      const int fo = side ? P : 0;
+      // own (s2 = 0) and neighbour (1) traces along the face's fast axis:
+      // T1[s2][f][i2][k1]
+      for (int t = lane; t < EPW * 2 * 5 * N1; t += 64) {
+        const int el = t / (10 * N1), r = t - el * (10 * N1), s2 = r / (5 * N1), r2 = r - s2 * (5 * N1);
+        const int f = r2 / N1, i2 = r2 - f * N1;
+        double* out = sS + el * C::L_S + ((s2 * 5 + f) * N1 + i2) * NQP;
+        if (s2 == 0)
+          line<NQ, N1>(B, sQ + (el * 5 + f) * NP + face_node<N1>(d, fo, 0, i2), d == 0 ? N1 : 1, out, 1);
+        else
+          line<NQ, N1>(B, sF + ((el * 6 + face) * 5 + f) * NF2 + i2 * N1, 1, out, 1);
       }
-    }
-    __syncthreads();
-    // along the slow axis: line (el, s2, f, kf)
-    for (int t = tid; t < EPB * 2 * 5 * NQ; t += 256) {
-      const int g = t / NQ, kf = t - g * NQ;  // g = (el, s2, f)
-      line<NQ, N1>(B, sR1 + g * (N1 * NQ) + kf, NQ, sR2 + g * (NQ * NQ) + kf, NQ);
-    }
-    __syncthreads();
-    // Lax-Friedrichs flux at the face quad points
-    double* fh = sR1 + EPB * 2 * 5 * N1 * NQ;  // after the face interpolation buffer
-    for (int t = tid; t < EPB * NQ * NQ; t += 256) {
-      const int el = t / (NQ * NQ), k2 = t - el * (NQ * NQ);
-      double qm[5], qp[5];
+      __syncthreads();
+      // along the slow axis in registers, then the Lax-Friedrichs flux
+      double fh[5];
+      if (col) {
+        double qm[5], qp[5];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        qm[f] = sR2[((el * 2 + 0) * 5 + f) * (NQ * NQ) + k2];
-        qp[f] = sR2[((el * 2 + 1) * 5 + f) * (NQ * NQ) + k2];
-      }
-      double um, vm, wm, pm, up, vp, wp, pp;
-      prim(qm, A.gamma, um, vm, wm, pm);
-      prim(qp, A.gamma, up, vp, wp, pp);
-      const double udm = d == 0 ? um : d == 1 ? vm : wm, udp = d == 0 ? up : d == 1 ? vp : wp;
-      const double lam = fmax(fabs(udm) + sqrt(A.gamma * pm / qm[0]), fabs(udp) + sqrt(A.gamma * pp / qp[0]));
-      const double sg = side ? 0.5 : -0.5;
+        for (int f = 0; f < 5; ++f) {
+          double sm = 0.0, sp = 0.0;
 #pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        const double Fm = (f == 4 ? qm[4] + pm : qm[f]) * udm + (f == 1 + d ? pm : 0.0);
-        const double Fp = (f == 4 ? qp[4] + pp : qp[f]) * udp + (f == 1 + d ? pp : 0.0);
-        fh[(el * 5 + f) * (NQ * NQ) + k2] = sg * (Fm + Fp) + 0.5 * lam * (qm[f] - qp[f]);
-      }
-    }
-    __syncthreads();
-    // projection along the fast axis: line (el, f, ks), NQ -> N1
-    double* g1 = sF + EPB * 6 * 5 * NF2;  // after the neighbour face nodes
-    for (int t = tid; t < EPB * 5 * NQ; t += 256)
-      line<N1, NQ>(Pm, fh + t * NQ, 1, g1 + t * N1, 1);
-    __syncthreads();
-    // along the slow axis and the lift: line (el, f, fast), NQ -> N1; each
-    // output (slow, fast) is lifted along the face's normal line
-    for (int t = tid; t < EPB * 5 * N1; t += 256) {
-      const int ef = t / N1, fast = t - ef * N1, el = ef / 5, f = ef - el * 5;
-      double g2[N1];
-      line<N1, NQ>(Pm, g1 + ef * (NQ * N1) + fast, N1, g2, 1);
-      const int e = e0 + el < E ? e0 + el : E - 1;
-      const int cx = e % A.nx, cxy = e / A.nx;
-      const double ihd = d == 0 ? A.ih[cx] : d == 1 ? A.ih[A.nx + cxy % A.ny] : A.ih[A.nx + A.ny + cxy / A.ny];
-      double* out = sOut + (el * 5 + f) * NP;
+          for (int i2 = 0; i2 < N1; ++i2) {
+            sm = fma(Brow[i2], cS[((0 * 5 + f) * N1 + i2) * NQP + ck1], sm);
+            sp = fma(Brow[i2], cS[((1 * 5 + f) * N1 + i2) * NQP + ck1], sp);
+          }
+          qm[f] = sm;
+          qp[f] = sp;
+        }
+        const double irm = 1.0 / qm[0], irp = 1.0 / qp[0];
+        const double um = qm[1] * irm, vm = qm[2] * irm, wm = qm[3] * irm;
+        const double up = qp[1] * irp, vp = qp[2] * irp, wp = qp[3] * irp;
+        const double pm = (g - 1.0) * (qm[4] - 0.5 * (qm[1] * um + qm[2] * vm + qm[3] * wm));
+        const double pp = (g - 1.0) * (qp[4] - 0.5 * (qp[1] * up + qp[2] * vp + qp[3] * wp));
+        const double udm = d == 0 ? um : d == 1 ? vm : wm, udp = d == 0 ? up : d == 1 ? vp : wp;
+        const double lam = fmax(fabs(udm) + sqrt(g * pm * irm), fabs(udp) + sqrt(g * pp * irp));
+        const double sg = side ? 0.5 : -0.5;
 #pragma unroll
-      for (int slow = 0; slow < N1; ++slow) {
-        const double gv = ihd * g2[slow];
-#pragma unroll
-        for (int i = 0; i < N1; ++i) {
-          const int node = d == 0 ? i + N1 * (fast + N1 * slow) : d == 1 ? fast + N1 * (i + N1 * slow)
-                                                                         : fast + N1 * (slow + N1 * i);
-          out[node] -= lift[i * 2 + side] * gv;
+        for (int f = 0; f < 5; ++f) {
+          const double Fm = (f == 4 ? qm[4] + pm : qm[f]) * udm + (f == 1 + d ? pm : 0.0);
+          const double Fp = (f == 4 ? qp[4] + pp : qp[f]) * udp + (f == 1 + d ? pp : 0.0);
+          fh[f] = sg * (Fm + Fp) + 0.5 * lam * (qm[f] - qp[f]);
         }
       }
+      __syncthreads();  // T1 read: Fh takes its place
+      if (col) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) cS[(f * NQ + ck2) * NQP + ck1] = fh[f];
+      }
+      __syncthreads();
+      // projection along the fast axis: U[f][k2][i1]
+      for (int t = lane; t < EPW * 5 * NQ; t += 64) {
+        const int el = t / (5 * NQ), r = t - el * (5 * NQ);  // r = f NQ + k2
+        double* base = sS + el * C::L_S;
+        line<N1, NQ>(Pm, base + r * NQP, 1, base + C::X_U + r * N1P, 1);
+      }
+      __syncthreads();
+      // along the slow axis, over the neighbour slice: g[f][i2][i1]
+      for (int t = lane; t < EPW * 5 * N1; t += 64) {
+        const int el = t / (5 * N1), r = t - el * (5 * N1), f = r / N1, i1 = r - f * N1;
+        line<N1, NQ>(Pm, sS + el * C::L_S + C::X_U + f * NQ * N1P + i1, N1P,
+                     sF + ((el * 6 + face) * 5 + f) * NF2 + i1, N1);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
-  // (4) store or stage update (coalesced per field)
+  // (2) the state at the volume quad points, in this lane's column: 1 / rho,
+  // the momenta, the pressure and E + p at its NQ points
+  double irho[NQ], mx[NQ], my[NQ], mz[NQ], pr[NQ], en[NQ];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    // along a: W1[cb][ka]
+    for (int t = lane; t < EPW * NF2; t += 64) {
+      const int el = t / NF2, cb = t - el * NF2;
+      line<NQ, N1>(B, sQ + (el * 5 + f) * NP + cb * N1, 1, sS + el * C::L_S + cb * NQP, 1);
+    }
+    __syncthreads();
+    // along b: W2[c][kb][ka]
+    for (int t = lane; t < EPW * N1 * NQ; t += 64) {
+      const int el = t / (N1 * NQ), r = t - el * (N1 * NQ), c = r / NQ, ka = r - c * NQ;
+      double* base = sS + el * C::L_S;
+      line<NQ, N1>(B, base + c * N1 * NQP + ka, NQP, base + NF2 * NQP + c * QF + ka, NQ);
+    }
+    __syncthreads();
+    // along c, in registers (the next field's first pass writes W1 only, and
+    // W2 is rewritten only after the barrier that follows it)
+    double x[N1], z[NQ];
+#pragma unroll
+    for (int c = 0; c < N1; ++c) x[c] = cS[NF2 * NQP + c * QF + ck];
+    line_r<NQ, N1>(B, x, z);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      if (f == 0) irho[k] = 1.0 / z[k];
+      if (f == 1) mx[k] = z[k];
+      if (f == 2) my[k] = z[k];
+      if (f == 3) mz[k] = z[k];
+      if (f == 4) {
+        const double u = mx[k] * irho[k], v = my[k] * irho[k], w = mz[k] * irho[k];
+        pr[k] = (g - 1.0) * (z[k] - 0.5 * (mx[k] * u + my[k] * v + mz[k] * w));
+        en[k] = z[k] + pr[k];
+      }
+    }
+  }
+
+  // (3) volume term and the lifted face terms, field by field.  Output line
+  // of this lane: element lel, nodes (a, b = lb, c = lc), a = 0..p.
+  const bool own = lane < EPW * NF2;
+  const int lel = own ? lane / NF2 : 0;
+  const int lcb = own ? lane - lel * NF2 : 0;  // idle lanes keep in-bounds addresses
+  const int lc = lcb / N1, lb = lcb - lc * N1;
+  const int le = e0 + lel < E ? e0 + lel : E - 1;
+  const bool lvalid = own && e0 + lel < E;
+  const int lcx = le % A.nx, lcxy = le / A.nx;
+  const double ihx = A.ih[lcx], ihy = A.ih[A.nx + lcxy % A.ny], ihz = A.ih[A.nx + A.ny + lcxy / A.ny];
+  const double lb0 = lift[lb * 2], lb1 = lift[lb * 2 + 1], lc0 = lift[lc * 2], lc1 = lift[lc * 2 + 1];
+  const double* lS = sS + lel * C::L_S;
+  const double* lF = sF + lel * (6 * 5 * NF2);
   bool bad = false;
 #pragma unroll
-  for (int u = 0; u < C::KR; ++u) {
-    const int t = tid + 256 * u;
-    if (t < EPB * 5 * NP) {
-      const int f = t / (EPB * NP), r = t - f * (EPB * NP);
-      const int el = r / NP, n = r - el * NP;
-      if (e0 + el < E) {
-        const double val = sOut[(el * 5 + f) * NP + n];
-        const size_t gi = f * Es + static_cast<size_t>(e0 + el) * NP + n;
-        if (FUSED) {
-          const double rr = (A.a == 0.0 ? 0.0 : A.a * rv[u]) + A.dt * val;
-          const double qn = sQ[(el * 5 + f) * NP + n] + A.b * rr;
-          A.res[gi] = rr;
-          A.qout[gi] = qn;
-          bad |= nonfinite(qn);
-        } else {
-          A.rhs[gi] = val;
-          bad |= nonfinite(val);
+  for (int f = 0; f < 5; ++f) {
+    const size_t gbase = f * Es + static_cast<size_t>(le) * NP + lcb * N1;
+    double rv[N1];
+    if (FUSED) {
+#pragma unroll
+      for (int a = 0; a < N1; ++a) rv[a] = A.a != 0.0 ? A.res_in[gbase + a] : 0.0;
+    }
+    double acc[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) acc[a] = 0.0;
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+      // flux component d of field f at the column's points, projected along c
+      // (S for d = z, P otherwise): Hs[c][kb][ka]
+      if (col) {
+        double F[NQ], H[N1];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+          const double md = d == 0 ? mx[k] : d == 1 ? my[k] : mz[k];
+          const double ud = md * irho[k];
+          F[k] = f == 0 ? md
+                 : f == 4 ? en[k] * ud
+                          : (f == 1 ? mx[k] : f == 2 ? my[k] : mz[k]) * ud + (f == 1 + d ? pr[k] : 0.0);
+        }
+        line_r<N1, NQ>(d == 2 ? S : Pm, F, H);
+#pragma unroll
+        for (int c = 0; c < N1; ++c) cS[c * QF + ck] = H[c];
+      }
+      __syncthreads();
+      // along b (S for d = y): Gs[c][b][ka]
+      for (int t = lane; t < EPW * N1 * NQ; t += 64) {
+        const int el = t / (N1 * NQ), r = t - el * (N1 * NQ), c = r / NQ, ka = r - c * NQ;
+        double* base = sS + el * C::L_S;
+        line<N1, NQ>(d == 1 ? S : Pm, base + c * QF + ka, NQ, base + N1 * QF + c * N1 * NQP + ka, NQP);
+      }
+      __syncthreads();
+      // along a (S for d = x), into this lane's output line
+      if (own) {
+        double x[NQ], y[N1];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) x[k] = lS[N1 * QF + lcb * NQP + k];
+        line_r<N1, NQ>(d == 0 ? S : Pm, x, y);
+        const double ih = d == 0 ? ihx : d == 1 ? ihy : ihz;
+#pragma unroll
+        for (int a = 0; a < N1; ++a) acc[a] = fma(ih, y[a], acc[a]);
+      }
+      // the next component's column pass writes Hs only, whose last reads
+      // came before the barrier above; Gs is rewritten after the next one
+    }
+    if (own) {
+      // lifted face fluxes: x faces at (i1, i2) = (b, c), y at (a, c), z at (a, b)
+      const double* gx0 = lF + (0 * 5 + f) * NF2;
+      const double* gx1 = lF + (1 * 5 + f) * NF2;
+      const double* gy0 = lF + (2 * 5 + f) * NF2;
+      const double* gy1 = lF + (3 * 5 + f) * NF2;
+      const double* gz0 = lF + (4 * 5 + f) * NF2;
+      const double* gz1 = lF + (5 * 5 + f) * NF2;
+      const double sx0 = gx0[lc * N1 + lb], sx1 = gx1[lc * N1 + lb];
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const double sx = lift[a * 2] * sx0 + lift[a * 2 + 1] * sx1;
+        const double sy = lb0 * gy0[lc * N1 + a] + lb1 * gy1[lc * N1 + a];
+        const double sz = lc0 * gz0[lb * N1 + a] + lc1 * gz1[lb * N1 + a];
+        const double out = acc[a] - (ihx * sx + ihy * sy + ihz * sz);
+        if (lvalid) {
+          if (FUSED) {
+            const double rr = (A.a == 0.0 ? 0.0 : A.a * rv[a]) + A.dt * out;
+            const double qn = sQ[(lel * 5 + f) * NP + lcb * N1 + a] + A.b * rr;
+            if (A.res) A.res[gbase + a] = rr;
+            A.qout[gbase + a] = qn;
+            bad |= nonfinite(qn);
+          } else {
+            A.rhs[gbase + a] = out;
+            bad |= nonfinite(out);
+          }
         }
       }
     }
@@ -326,12 +428,12 @@ __global__ __launch_bounds__(256) void hex_oi_kernel(OiArgs A) {
 template <int P>
 dg_status launch_oi_p(const HexMesh& m, const OiArgs& A, bool fused, hipStream_t s) {
   using C = OiCfg<P>;
-  static_assert(C::PER_EL * C::EPB * 8 <= 65536, "LDS budget");
-  const int64_t blocks = (m.E + C::EPB - 1) / C::EPB;
+  static_assert(C::PER_EL * C::EPW * 8 <= 65536, "LDS budget");
+  const int64_t blocks = (m.E + C::EPW - 1) / C::EPW;
   if (fused)
-    hipLaunchKernelGGL((hex_oi_kernel<P, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+    hipLaunchKernelGGL((hex_oi_kernel<P, true>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, s, A);
   else
-    hipLaunchKernelGGL((hex_oi_kernel<P, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+    hipLaunchKernelGGL((hex_oi_kernel<P, false>), dim3(static_cast<unsigned>(blocks)), dim3(64), 0, s, A);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? DG_OK : hip_fail(e, "hex overintegrated rhs launch");
 }
@@ -340,11 +442,12 @@ dg_status launch_oi_p(const HexMesh& m, const OiArgs& A, bool fused, hipStream_t
 
 int hex_oi_points(int p) { return oi_nq(p); }
 
-dg_status launch_rhs_hex_oi(const HexMesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
-                            double a, double b, double dt, bool fused, hipStream_t s) {
+dg_status launch_rhs_hex_oi(const HexMesh& m, double gamma, const double* q, double* rhs, const double* res_in,
+                            double* res, double* q_out, double a, double b, double dt, bool fused, hipStream_t s) {
   OiArgs A;
   A.q = q;
   A.rhs = rhs;
+  A.res_in = res_in;
   A.res = res;
   A.qout = q_out;
   A.ih = m.d_ih;

@@ -110,19 +110,49 @@ struct Mesh {
   dg_launch_config launch[3] = {{4, 1}, {4, 1}, {4, 1}};
 };
 
+// Buffers of stage s of a fused five-stage LSRK step over the caller's state
+// q and two state-sized work buffers w1, w2.  A stage reads its state from
+// q_in (neighbour traces included) and writes the new state to another
+// buffer; the residual is read and written entry by entry, so it may move
+// between buffers and share one with the new state.  Rotating the three
+// buffers this way leaves the fifth stage's state in q without a copy:
+//   stage  q_in  res_in  res_out  q_out
+//     1     q     -       w1       w2
+//     2     w2    w1      w1       q
+//     3     q     w1      w1       w2
+//     4     w2    w1      q        w1
+//     5     w1    q       -        q
+struct LsrkBuffers {
+  const double* q_in;
+  const double* res_in;
+  double* res_out;
+  double* q_out;
+};
+inline LsrkBuffers lsrk_buffers(int s, double* q, double* w1, double* w2) {
+  switch (s) {
+    case 0: return {q, w1, w1, w2};
+    case 1: return {w2, w1, w1, q};
+    case 2: return {q, w1, w1, w2};
+    case 3: return {w2, w1, q, w1};
+    default: return {w1, q, nullptr, q};
+  }
+}
+
 // kernel launchers (defined in the .hip files)
 // RHS of q; with fused_lsrk the result goes through the stage update
-// (res <- a res + dt rhs; q_out <- q + b res) instead of being stored in rhs.
-dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, double* rhs, double* res,
-                                double* q_out, double a, double b, double dt, bool fused_lsrk, hipStream_t s);
-// Same, with the contraction in FP32 or split BF16.
-dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, const double* q, double* rhs,
+// (res <- a res_in + dt rhs; q_out <- q + b res) instead of being stored in
+// rhs, res being skipped when null.
+dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, double* rhs, const double* res_in,
                                 double* res, double* q_out, double a, double b, double dt, bool fused_lsrk,
                                 hipStream_t s);
+// Same, with the contraction in FP32 or split BF16.
+dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, const double* q, double* rhs,
+                                const double* res_in, double* res, double* q_out, double a, double b, double dt,
+                                bool fused_lsrk, hipStream_t s);
 dg_status launch_lsrk_update(int64_t n, double a, double b, double dt, const double* rhs, double* res,
                              double* q, hipStream_t s);
-// One LSRK(5,4) Euler step of q in place; work = [residual | second state
-// buffer] (2 x 5 E Np doubles); the mesh's device is current.
+// One LSRK(5,4) Euler step of q in place; work = two state-sized buffers
+// (2 x 5 E Np doubles); the mesh's device is current.
 dg_status rk_step_euler(const Mesh& m, double gamma, dg_precision prec, double* q, double* work, double dt,
                         hipStream_t stream);
 // dg_rhs / dg_rk_step with model 1 (reacting Navier-Stokes), prm->work scratch.

@@ -71,8 +71,9 @@ constexpr bool lowp_lds_tables() { return P < 4; }
 struct LowArgs {
   const double* __restrict__ q;
   double* __restrict__ rhs;
-  double* __restrict__ res;
-  double* __restrict__ qout;
+  const double* res_in;  // residual read by the fused stage (may alias res or qout)
+  double* res;           // residual written by the fused stage (null: not stored)
+  double* qout;
   const double* __restrict__ geo;
   const int2* __restrict__ conn;
   const float* __restrict__ op32;
@@ -345,7 +346,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
             }
       }
       __builtin_amdgcn_wave_barrier();
-      store_tile<FUSED, TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt, A.flags);
+      store_tile<FUSED, TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res_in, A.res, A.qout, q, A.a, A.b, A.dt, A.flags);
     } else if constexpr (!FUSED) {
       if (valid) {
         bool bad = false;
@@ -376,7 +377,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
           for (int v = 0; v < 4; ++v) {
             const int row = out_row(rb, v);
             const int64_t idx = f * Es + e * C::NP + (row < C::NP ? row : C::NP - 1);  // clamped: unconditional
-            rv[rb][v] = A.a != 0.0 ? A.res[idx] : 0.0;
+            rv[rb][v] = A.a != 0.0 ? A.res_in[idx] : 0.0;
             qv[rb][v] = q[idx];
           }
 #pragma unroll

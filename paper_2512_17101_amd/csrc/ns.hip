@@ -391,7 +391,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
 #pragma unroll
     for (int k = 0; k < R::FH; ++k) {
       const int64_t at = (f0 + k) * Es + idx;
-      rv[k] = A.a != 0.0 ? A.res[at] : 0.0;
+      rv[k] = A.a != 0.0 ? A.res_in[at] : 0.0;
       qv[k] = A.q[at];
     }
 #pragma unroll

@@ -13,8 +13,9 @@ struct NsArgs {
   const double* T;      // [E][Np] temperatures of q
   double* sigma;        // [E][Np][33] lifted gradients, entry 3 c + d = d v_c / d x_d
   double* rhs;          // [12][E][Np] (unfused)
-  double* res;          // fused stage: res <- a res + dt rhs
-  double* qout;         //              qout <- q + b res
+  const double* res_in; // fused stage: res <- a res_in + dt rhs (res skipped when null)
+  double* res;          //              qout <- q + b res
+  double* qout;         // (res_in, res and qout may share a buffer: entry-wise)
   const double* geo;    // [9][Epad]
   const int2* conn;     // [4][Epad]
   const double* opT;    // [3 Np + 4 Nfp][Np]: D_a[i][j] at row a Np + j, LIFT[i][m] at row 3 Np + m

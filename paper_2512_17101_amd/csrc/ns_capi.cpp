@@ -91,19 +91,19 @@ namespace {
 dg_status ns_step(const Mesh& m, const dg_params* prm, double* q, double* T, bool T_valid, double* work, double dt,
                   double tol, int max_iter, hipStream_t stream) {
   const size_t n = static_cast<size_t>(m.E) * m.Np;
-  double* res = work;
-  double* buf[2] = {q, work + kFields * n};
   double* sigma = work + 2 * kFields * n;
   int32_t* iters = reinterpret_cast<int32_t*>(work + (2 * kFields + kGrad) * n);
   const ThermoTable& th = thermo_table(prm->thermo);
   NsArgs A = make_args(m, prm);
   A.sigma = sigma;
   A.T = T;
-  A.res = res;
   A.dt = dt;
   for (int s = 0; s < 5; ++s) {
-    A.q = buf[s & 1];
-    A.qout = buf[(s + 1) & 1];
+    const LsrkBuffers B = lsrk_buffers(s, q, work, work + kFields * n);
+    A.q = B.q_in;
+    A.res_in = B.res_in;
+    A.res = B.res_out;
+    A.qout = B.q_out;
     A.a = kLsrkA[s];
     A.b = kLsrkB[s];
     dg_status st = launch_temperature(th, static_cast<int64_t>(n), A.q, (s > 0 || T_valid) ? T : nullptr, kTdefault, T,
@@ -114,7 +114,6 @@ dg_status ns_step(const Mesh& m, const dg_params* prm, double* q, double* T, boo
     st = launch_ns_rhs(m.p, A, true, stream);
     if (st != DG_OK) return st;
   }
-  DG_HIP(hipMemcpyAsync(q, buf[1], kFields * n * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return DG_OK;
 }
 

@@ -43,8 +43,9 @@ struct Cfg {
 struct RhsArgs {
   const double* __restrict__ q;
   double* __restrict__ rhs;
-  double* __restrict__ res;
-  double* __restrict__ qout;
+  const double* res_in;  // residual read by the fused stage (may alias res or qout)
+  double* res;           // residual written by the fused stage (null: not stored)
+  double* qout;
   const double* __restrict__ geo;
   const int2* __restrict__ conn;
   const double* __restrict__ op;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ?
     }
   }
   __builtin_amdgcn_wave_barrier();
-  store_tile<FUSED, TL::TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res, A.qout, q, A.a, A.b, A.dt, A.flags);
+  store_tile<FUSED, TL::TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res_in, A.res, A.qout, q, A.a, A.b, A.dt, A.flags);
 }
 
 template <int P, int W>
@@ -255,11 +256,12 @@ dg_status launch_p(const Mesh& m, const RhsArgs& args, bool fused, hipStream_t s
 
 }  // namespace
 
-dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, double* rhs, double* res, double* q_out,
-                                double a, double b, double dt, bool fused, hipStream_t s) {
+dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, double* rhs, const double* res_in,
+                                double* res, double* q_out, double a, double b, double dt, bool fused, hipStream_t s) {
   RhsArgs A;
   A.q = q;
   A.rhs = rhs;
+  A.res_in = res_in;
   A.res = res;
   A.qout = q_out;
   A.geo = m.d_geo;

@@ -102,11 +102,12 @@ LowpLayout lowp_layout(int p) {
 }
 
 dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, const double* q, double* rhs,
-                                double* res, double* q_out, double a, double b, double dt, bool fused,
-                                hipStream_t s) {
+                                const double* res_in, double* res, double* q_out, double a, double b, double dt,
+                                bool fused, hipStream_t s) {
   LowArgs A;
   A.q = q;
   A.rhs = rhs;
+  A.res_in = res_in;
   A.res = res;
   A.qout = q_out;
   A.geo = m.d_geo;

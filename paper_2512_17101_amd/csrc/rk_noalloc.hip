@@ -1,5 +1,5 @@
 // One LSRK(5,4) Euler step that allocates nothing: dg_rk_step with its
-// residual and second state buffer in a fixed device array instead of a
+// two state-sized work buffers in a fixed device array instead of a
 // caller workspace, for callers that cannot allocate device memory.
 //
 // The array is a file-scope device variable: the code object reserves it on
