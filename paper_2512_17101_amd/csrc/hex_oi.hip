@@ -425,6 +425,176 @@ __global__ __launch_bounds__(64) void hex_oi_kernel(OiArgs A) {
   raise_flag(A.flags, bad, kFlagNonFinite);
 }
 
+// One face of the p = 1 element: Fhat at the face's 3 x 3 quad points,
+// lifted onto the element's nodes (direction and side at compile time, so
+// that every register-array index is a constant).
+template <int d, int side>
+__device__ inline void p1_face(const OiArgs& A, int ec, size_t Es, double ihx, double ihy, double ihz,
+                               const double (&q)[5][8], double (&out)[5][8]) {
+  constexpr int NQ = 3;
+  const double* __restrict__ B = A.op;
+  const double* __restrict__ Pm = A.op + 12;
+  const double* __restrict__ lift = A.op + 18;
+  const double g = A.gamma;
+  const int fo = side, fn = 1 - side;  // own / neighbour node coordinate along d
+  const double ihd = d == 0 ? ihx : d == 1 ? ihy : ihz;
+  const int en = face_neighbour(ec, d, side, A.nx, A.ny, A.nz);
+  double qn[5][4];
+#pragma unroll
+  for (int f = 0; f < 5; ++f)
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      qn[f][m] = A.q[f * Es + static_cast<size_t>(en) * 8 + face_node<2>(d, fn, m & 1, m >> 1)];
+  const double sg = side ? 0.5 : -0.5;
+#pragma unroll 1
+  for (int k2 = 0; k2 < NQ; ++k2)
+#pragma unroll 1
+    for (int k1 = 0; k1 < NQ; ++k1) {
+      double wf[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) wf[m] = B[k1 * 2 + (m & 1)] * B[k2 * 2 + (m >> 1)];
+      double qm[5], qp[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        double tm = 0.0, tp = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          tm = fma(wf[m], q[f][face_node<2>(d, fo, m & 1, m >> 1)], tm);
+          tp = fma(wf[m], qn[f][m], tp);
+        }
+        qm[f] = tm;
+        qp[f] = tp;
+      }
+      const double irm = 1.0 / qm[0], irp = 1.0 / qp[0];
+      const double um = qm[1] * irm, vm = qm[2] * irm, wm = qm[3] * irm;
+      const double up = qp[1] * irp, vp = qp[2] * irp, wp = qp[3] * irp;
+      const double pm = (g - 1.0) * (qm[4] - 0.5 * (qm[1] * um + qm[2] * vm + qm[3] * wm));
+      const double pp = (g - 1.0) * (qp[4] - 0.5 * (qp[1] * up + qp[2] * vp + qp[3] * wp));
+      const double udm = d == 0 ? um : d == 1 ? vm : wm, udp = d == 0 ? up : d == 1 ? vp : wp;
+      const double lam = fmax(fabs(udm) + sqrt(g * pm * irm), fabs(udp) + sqrt(g * pp * irp));
+      double fh[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        const double Fm = (f == 4 ? qm[4] + pm : qm[f]) * udm + (f == 1 + d ? pm : 0.0);
+        const double Fp = (f == 4 ? qp[4] + pp : qp[f]) * udp + (f == 1 + d ? pp : 0.0);
+        fh[f] = ihd * (sg * (Fm + Fp) + 0.5 * lam * (qm[f] - qp[f]));
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double pw = Pm[(m & 1) * 3 + k1] * Pm[(m >> 1) * 3 + k2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const double cf = lift[i * 2 + side] * pw;
+          const int node = face_node<2>(d, i, m & 1, m >> 1);
+#pragma unroll
+          for (int f = 0; f < 5; ++f) out[f][node] = fma(-cf, fh[f], out[f][node]);
+        }
+      }
+    }
+}
+
+// p = 1: one lane per element with the element in registers.  A quad line
+// has three points and a node line two, so the wave-per-element passes spend
+// more on LDS round trips and per-line index arithmetic than on the
+// contractions; here each quad point is evaluated directly: the eight
+// interpolation weights B_ka,a B_kb,b B_kc,c, the flux there, and its
+// projection onto the eight nodes with the coefficients (S x P x P, P x S x P,
+// P x P x S)(2 / h).  The table entries are uniform (scalar loads).
+template <bool FUSED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void hex_oi_p1_kernel(OiArgs A) {
+  constexpr int NQ = 3;
+  const double* __restrict__ B = A.op;            // [3][2]
+  const double* __restrict__ S = A.op + 6;        // [2][3]
+  const double* __restrict__ Pm = A.op + 12;      // [2][3]
+  const double* __restrict__ lift = A.op + 18;    // [2][2]
+  const int E = A.E;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = e < E;
+  const int ec = valid ? e : E - 1;
+  const size_t Es = static_cast<size_t>(E) * 8;
+  const double g = A.gamma;
+  double q[5][8];
+#pragma unroll
+  for (int f = 0; f < 5; ++f)
+#pragma unroll
+    for (int n = 0; n < 8; ++n) q[f][n] = A.q[f * Es + static_cast<size_t>(ec) * 8 + n];
+  const int cx = ec % A.nx, cxy = ec / A.nx;
+  const double ihx = A.ih[cx], ihy = A.ih[A.nx + cxy % A.ny], ihz = A.ih[A.nx + A.ny + cxy / A.ny];
+  double out[5][8];
+#pragma unroll
+  for (int f = 0; f < 5; ++f)
+#pragma unroll
+    for (int n = 0; n < 8; ++n) out[f][n] = 0.0;
+
+  // volume: sum over the quad points of the projected fluxes
+#pragma unroll 1
+  for (int kc = 0; kc < NQ; ++kc)
+#pragma unroll 1
+    for (int kb = 0; kb < NQ; ++kb)
+#pragma unroll 1
+      for (int ka = 0; ka < NQ; ++ka) {
+        double z[5];
+        {
+          double w[8];
+#pragma unroll
+          for (int n = 0; n < 8; ++n) w[n] = B[ka * 2 + (n & 1)] * B[kb * 2 + ((n >> 1) & 1)] * B[kc * 2 + (n >> 2)];
+#pragma unroll
+          for (int f = 0; f < 5; ++f) {
+            double t = 0.0;
+#pragma unroll
+            for (int n = 0; n < 8; ++n) t = fma(w[n], q[f][n], t);
+            z[f] = t;
+          }
+        }
+        const double ir = 1.0 / z[0];
+        const double u = z[1] * ir, v = z[2] * ir, w = z[3] * ir;
+        const double pr = (g - 1.0) * (z[4] - 0.5 * (z[1] * u + z[2] * v + z[3] * w));
+        const double en = z[4] + pr;
+        // (2 / h_d) F_d of the five fields
+        const double Fx[5] = {ihx * z[1], ihx * (z[1] * u + pr), ihx * (z[2] * u), ihx * (z[3] * u), ihx * (en * u)};
+        const double Fy[5] = {ihy * z[2], ihy * (z[1] * v), ihy * (z[2] * v + pr), ihy * (z[3] * v), ihy * (en * v)};
+        const double Fz[5] = {ihz * z[3], ihz * (z[1] * w), ihz * (z[2] * w), ihz * (z[3] * w + pr), ihz * (en * w)};
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+          const int a = n & 1, b = (n >> 1) & 1, c = n >> 2;
+          const double cxn = S[a * 3 + ka] * Pm[b * 3 + kb] * Pm[c * 3 + kc];
+          const double cyn = Pm[a * 3 + ka] * S[b * 3 + kb] * Pm[c * 3 + kc];
+          const double czn = Pm[a * 3 + ka] * Pm[b * 3 + kb] * S[c * 3 + kc];
+#pragma unroll
+          for (int f = 0; f < 5; ++f) out[f][n] = fma(cxn, Fx[f], fma(cyn, Fy[f], fma(czn, Fz[f], out[f][n])));
+        }
+      }
+
+  // faces
+  p1_face<0, 0>(A, ec, Es, ihx, ihy, ihz, q, out);
+  p1_face<0, 1>(A, ec, Es, ihx, ihy, ihz, q, out);
+  p1_face<1, 0>(A, ec, Es, ihx, ihy, ihz, q, out);
+  p1_face<1, 1>(A, ec, Es, ihx, ihy, ihz, q, out);
+  p1_face<2, 0>(A, ec, Es, ihx, ihy, ihz, q, out);
+  p1_face<2, 1>(A, ec, Es, ihx, ihy, ihz, q, out);
+
+  bool bad = false;
+  if (valid) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+      for (int n = 0; n < 8; ++n) {
+        const size_t gi = f * Es + static_cast<size_t>(e) * 8 + n;
+        if (FUSED) {
+          const double rr = (A.a == 0.0 ? 0.0 : A.a * A.res_in[gi]) + A.dt * out[f][n];
+          const double qn = q[f][n] + A.b * rr;
+          if (A.res) A.res[gi] = rr;
+          A.qout[gi] = qn;
+          bad |= nonfinite(qn);
+        } else {
+          A.rhs[gi] = out[f][n];
+          bad |= nonfinite(out[f][n]);
+        }
+      }
+  }
+  raise_flag(A.flags, bad, kFlagNonFinite);
+}
+
 template <int P>
 dg_status launch_oi_p(const HexMesh& m, const OiArgs& A, bool fused, hipStream_t s) {
   using C = OiCfg<P>;
@@ -462,7 +632,15 @@ dg_status launch_rhs_hex_oi(const HexMesh& m, double gamma, const double* q, dou
   A.dt = dt;
   A.flags = device_flags();
   switch (m.p) {
-    case 1: return launch_oi_p<1>(m, A, fused, s);
+    case 1: {
+      const unsigned blocks = static_cast<unsigned>((m.E + 255) / 256);
+      if (fused)
+        hipLaunchKernelGGL((hex_oi_p1_kernel<true>), dim3(blocks), dim3(256), 0, s, A);
+      else
+        hipLaunchKernelGGL((hex_oi_p1_kernel<false>), dim3(blocks), dim3(256), 0, s, A);
+      const hipError_t e = hipGetLastError();
+      return e == hipSuccess ? DG_OK : hip_fail(e, "hex overintegrated rhs launch");
+    }
     case 2: return launch_oi_p<2>(m, A, fused, s);
     case 3: return launch_oi_p<3>(m, A, fused, s);
     case 4: return launch_oi_p<4>(m, A, fused, s);

@@ -182,13 +182,14 @@ def _oi_ratio(oi, gr, q, got):
 
 
 @pytest.mark.parametrize("p,dims", [(1, (5, 3, 4)), (2, (3, 4, 5)), (3, (4, 3, 3)), (4, (3, 3, 4)),
-                                    (1, (1, 2, 3)), (4, (2, 1, 1)), (4, (16, 16, 16))])
+                                    (1, (1, 2, 3)), (4, (2, 1, 1)), (4, (16, 16, 16)), (1, (9, 8, 7))])
 def test_hex_oi_rhs_matches_oracle(p, dims):
     """Every entry within K u T, K the longest chain of sums into an entry of
     the overintegrated form (oracle hex.oi_contraction_length) and T its term
-    magnitude; ragged grids, single-cell periodic directions, and a 16^3
-    p = 4 grid in the launch shape of the 48^3 benchmark (one element per
-    block)."""
+    magnitude; ragged grids, single-cell periodic directions, a 16^3 p = 4
+    grid in the launch shape of the 48^3 benchmark (one element per wave),
+    and 504 p = 1 elements (one element per lane: two 256-lane blocks, the
+    second ragged)."""
     dev = _dev()
     lines, gr, ops, X, q = _case(p, dims)
     oi = oh.oi_operators(p)
@@ -228,13 +229,14 @@ def test_hex_oi_rk_steps_track_oracle(p):
     assert np.all(err <= 1e-12)
 
 
-def test_hex_oi_full_size_conservation():
-    """The 48^3 p = 4 benchmark workload: the overintegrated RHS is finite
-    and conserves every field to 1e-13 of the absolute sum (a property of
-    the weak form at any size; element-by-element parity runs on the 16^3
-    grid in the same launch shape)."""
+@pytest.mark.parametrize("p,n", [(4, 48), (1, 120)])
+def test_hex_oi_full_size_conservation(p, n):
+    """The two benchmark workloads (48^3 at p = 4, 120^3 at p = 1): the
+    overintegrated RHS is finite and conserves every field to 1e-13 of the
+    absolute sum (a property of the weak form at any size; element-by-element
+    parity runs on the 16^3 p = 4 and 504-element p = 1 grids in the same
+    launch shapes)."""
     dev = _dev()
-    p, n = 4, 48
     lines = wl.rectilinear_box(n, 10.0, 0.05, 1002)
     gr = oh.grid(*lines)
     m = hexdg.HexMesh(p, *lines)
@@ -254,5 +256,5 @@ def test_hex_oi_full_size_conservation():
     # not depend on z), so the momentum components share the momentum's scale
     tot, scale = contrib.sum(axis=(1, 2)), np.abs(contrib).sum(axis=(1, 2))
     scale[1:4] = scale[1:4].max()
-    print(f"OI 48^3 p=4 conservation: {np.array2string(np.abs(tot) / scale, precision=2)}", flush=True)
+    print(f"OI {n}^3 p={p} conservation: {np.array2string(np.abs(tot) / scale, precision=2)}", flush=True)
     assert np.all(np.abs(tot) <= 1e-13 * scale)
