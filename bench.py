@@ -671,12 +671,20 @@ def shock_leg(dg, hexdg, wl, dev, stream, steps, warmup):
             ms_pstep = _time_ms(stream, lambda: hexdg.rk_step(m, qp, wplain, 0.0, dt, stream=stream), max(2, steps // 10))
         dg.synchronize(0, stream)
         viscous = int((eps > 0).sum().item())
+        # algorithmic bytes of the two passes per element: the state read by
+        # both, the rhs written, indicator and viscosity (16 + 8 B), and for
+        # the viscous elements G (3 x 5 x Np doubles) written once, read once
+        bytes_av = m.E * (120 * m.Np + 24) + viscous * 240 * m.Np
+        gbs_av = bytes_av / (ms_rhs * 1e-3) / 1e9
         out[name] = {"elements": m.E, "order": p, "viscous_elements": viscous,
                      "ms_indicator_and_viscous_flux": round(ms_flux, 4), "ms_rhs_with_av": round(ms_rhs, 4),
                      "ms_rhs_plain": round(ms_plain, 4), "ms_limiter": round(ms_lim, 4),
                      "ms_step_with_av_and_limiter": round(ms_step, 4), "ms_step_plain": round(ms_pstep, 4),
                      "value": round(nn * NF / (ms_rhs * 1e-3) / 1e9, 3),
                      "unit": "GDOF·fields/s (RHS with artificial viscosity)",
+                     "roofline": {"bound": "hbm", "achieved": round(gbs_av, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                  "frac": round(gbs_av / PEAK_HBM_GBS, 4), "bytes": int(bytes_av),
+                                  "kernels": "hex_av_flux_kernel + hex_rhs_kernel (viscous variant)"},
                      "state_finite": bool(torch.isfinite(qs).all()), "min_density_after_steps": float(qs[0].min())}
         del q, r, G, eps, work, wplain, ql, qs, qp
         m.close()

@@ -179,8 +179,12 @@ typedef struct {
                           p = 4 the FP64 kernel runs 2 and the FP32 / split
                           BF16 kernels 1, whatever is requested. */
   int rk_fused;        /* 1 = fused stage launches, 0 = RHS launch + update */
+  int lds_stage;       /* 1 = stage the state tile into LDS by direct
+                          global-to-LDS loads where that path exists (FP64
+                          and FP32 contractions, Np a multiple of 4, q
+                          16-byte aligned), 0 = through registers */
 } dg_launch_config;
-/* Initial configuration of every precision: {4, 1}.  Set and get are
+/* Initial configuration of every precision: {4, 1, 1}.  Set and get are
  * synchronous host calls that must not overlap calls running on the mesh. */
 dg_status dg_mesh_set_launch(dg_mesh m, dg_precision prec, const dg_launch_config* cfg);
 dg_status dg_mesh_get_launch(dg_mesh m, dg_precision prec, dg_launch_config* cfg);

@@ -13,9 +13,9 @@
 //                       positivity by scaling towards the cell average
 //                       (Zhang & Shu), with delta; elements that need no
 //                       limiting are not written.
-// The element reductions (energies, wave speed, averages, minima) are summed
-// by one thread per element in a fixed order, so results do not depend on
-// the launch.
+// The element reductions (energies, wave speed, averages, minima) run in a
+// fixed order (the indicator's at p >= 3 as eight strided partial sums and
+// their sum), so results do not depend on the launch.
 #include <cmath>
 
 #include "hex.hpp"
@@ -56,10 +56,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || P
     ShArgs A) {
   using C = ShCfg<P>;
   constexpr int N1 = C::N1, NP = C::NP, NFP = C::NFP, EPB = C::EPB;
+  constexpr int RW = NP >= 64 ? 8 : 1;  // partial sums per element in the reductions
+  static_assert(EPB * RW <= 256, "reduction threads");
   __shared__ double s_q[EPB][5][NP];
   __shared__ double s_J[EPB][6][5][NFP];
-  __shared__ double s_t[2][EPB * NP];  // modal passes, then reductions
-  __shared__ double s_r[3][EPB * NP];
+  __shared__ double s_t[2][EPB * NP];  // modal passes
+  __shared__ double s_r[3][EPB * NP];  // per-node energies and wave speeds
+  __shared__ double s_p[3][EPB * RW];  // their partial sums
   __shared__ double s_eps[EPB];
   const int tid = threadIdx.x;
   const int E = A.E;
@@ -72,11 +75,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || P
   const int idx = e * NP + ic;
   const size_t Es = static_cast<size_t>(E) * NP;
 
+  // (1) the indicator and the viscosity need only the element's own nodes.
+  // At p <= 2 (8 or 27 nodes, 32 or 9 elements per block) most blocks on a
+  // shock front hold a viscous element, and the neighbour traces are
+  // requested here already, so that their latency overlaps the indicator;
+  // at p >= 3 they are gathered only by blocks that need them.
+  constexpr bool kPrefetch = P <= 2;
   double qv[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) qv[f] = A.q[f * Es + idx];
   double qp[C::KF][5];
-  int ownn[C::KF];
+  int nbi[C::KF], ownn[C::KF];
 #pragma unroll
   for (int u = 0; u < C::KF; ++u) {
     const int s = tid + 256 * u < C::NS ? tid + 256 * u : C::NS - 1;
@@ -84,8 +93,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || P
     const int face = rem / NFP, m = rem - face * NFP;
     const int d = face >> 1, side = face & 1;
     const int ef = e0 + fl < E ? e0 + fl : E - 1;
-    const int cx = ef % A.nx, cxy = ef / A.nx, cy = cxy % A.ny, cz = cxy / A.ny;
-    const int cd = d == 0 ? cx : d == 1 ? cy : cz;
+    const int fx = ef % A.nx, fxy = ef / A.nx, fy = fxy % A.ny, fz = fxy / A.ny;
+    const int cd = d == 0 ? fx : d == 1 ? fy : fz;
     const int nd = d == 0 ? A.nx : d == 1 ? A.ny : A.nz;
     const int stride = d == 0 ? 1 : d == 1 ? A.nx : A.nx * A.ny;
     const int en = side ? (cd == nd - 1 ? ef - (nd - 1) * stride : ef + stride)
@@ -93,9 +102,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || P
     const int uu = m % N1, vv = m / N1;
     const int fo = side ? P : 0, fn = side ? 0 : P;
     ownn[u] = d == 0 ? nidx<N1>(fo, uu, vv) : d == 1 ? nidx<N1>(uu, fo, vv) : nidx<N1>(uu, vv, fo);
-    const int nn = d == 0 ? nidx<N1>(fn, uu, vv) : d == 1 ? nidx<N1>(uu, fn, vv) : nidx<N1>(uu, vv, fn);
+    nbi[u] = en * NP + (d == 0 ? nidx<N1>(fn, uu, vv) : d == 1 ? nidx<N1>(uu, fn, vv) : nidx<N1>(uu, vv, fn));
+    if constexpr (kPrefetch) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qp[u][f] = A.q[f * Es + static_cast<size_t>(en) * NP + nn];
+      for (int f = 0; f < 5; ++f) qp[u][f] = A.q[f * Es + nbi[u]];
+    }
   }
   const int cx = e % A.nx, cxy = e / A.nx;
   const double ihx = A.ih[cx], ihy = A.ih[A.nx + cxy % A.ny], ihz = A.ih[A.nx + A.ny + cxy / A.ny];
@@ -105,20 +116,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || P
   }
   __syncthreads();
 
-  // central jumps n_d (q+ - q-) / 2 of the face slots
-#pragma unroll
-  for (int u = 0; u < C::KF; ++u) {
-    const int s = tid + 256 * u;
-    if (s < C::NS) {
-      const int fl = s / (6 * NFP), rem = s - fl * (6 * NFP);
-      const int face = rem / NFP, m = rem - face * NFP;
-      const double hn = (face & 1) ? 0.5 : -0.5;
-#pragma unroll
-      for (int f = 0; f < 5; ++f) s_J[fl][face][f][m] = hn * (qp[u][f] - s_q[fl][f][ownn[u]]);
-    }
-  }
-
-  // indicator: modal coefficients of rho, three passes (a, b, c)
+  // modal coefficients of rho, three passes (a, b, c)
   const int a = ic % N1, bb = (ic / N1) % N1, c = ic / (N1 * N1);
   const double* Vi = A.sh;
   const int base = elc * NP;
@@ -151,12 +149,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || P
     }
   }
   __syncthreads();
+  // energies and the largest wave speed per element, in a fixed order:
+  // RW strided partial sums (RW = 1 below 64 nodes), then their sum
+  if (tid < EPB * RW) {
+    const int re = tid / RW, rk = tid - re * RW;
+    double num = 0.0, den = 0.0, lam = 0.0;
+    for (int k = rk; k < NP; k += RW) {
+      den += s_r[0][re * NP + k];
+      num += s_r[1][re * NP + k];
+      lam = fmax(lam, s_r[2][re * NP + k]);
+    }
+    s_p[0][tid] = den;
+    s_p[1][tid] = num;
+    s_p[2][tid] = lam;
+  }
+  __syncthreads();
   if (tid < EPB) {
     double num = 0.0, den = 0.0, lam = 0.0;
-    for (int k = 0; k < NP; ++k) {
-      den += s_r[0][tid * NP + k];
-      num += s_r[1][tid * NP + k];
-      lam = fmax(lam, s_r[2][tid * NP + k]);
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+      den += s_p[0][tid * RW + k];
+      num += s_p[1][tid * RW + k];
+      lam = fmax(lam, s_p[2][tid * RW + k]);
     }
     const int ee = e0 + tid < E ? e0 + tid : E - 1;
     const int ex = ee % A.nx, exy = ee / A.nx;
@@ -175,14 +189,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || P
   }
   __syncthreads();
 
-  // lifted gradients and the viscous flux, per field; an inviscid element
-  // (eps = 0, most of them) has G = 0, which is neither formed nor stored:
-  // the right-hand side reads G only where eps > 0
-  const double epsv = s_eps[elc];
+  // (2) lifted gradients and the viscous flux, per field, only in blocks
+  // with a viscous element: an inviscid element (eps = 0, most of them) has
+  // G = 0, which is neither formed nor stored (the right-hand side reads G
+  // only where eps > 0), so most blocks end here without gathering any
+  // neighbour trace
   bool any = false;
 #pragma unroll
   for (int k = 0; k < EPB; ++k) any |= s_eps[k] > 0.0;
   if (!any) return;
+  const double epsv = s_eps[elc];
+  // central jumps n_d (q+ - q-) / 2 of the block's face slots
+  if constexpr (!kPrefetch) {
+#pragma unroll
+    for (int u = 0; u < C::KF; ++u)
+#pragma unroll
+      for (int f = 0; f < 5; ++f) qp[u][f] = A.q[f * Es + nbi[u]];
+  }
+#pragma unroll
+  for (int u = 0; u < C::KF; ++u) {
+    const int s = tid + 256 * u;
+    if (s < C::NS) {
+      const int fl = s / (6 * NFP), rem = s - fl * (6 * NFP);
+      const int face = rem / NFP, m = rem - face * NFP;
+      const double hn = (face & 1) ? 0.5 : -0.5;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) s_J[fl][face][f][m] = hn * (qp[u][f] - s_q[fl][f][ownn[u]]);
+    }
+  }
+  __syncthreads();
   const double* D1 = A.op;
   const double* lift = A.op + N1 * N1;
 #pragma unroll 1

@@ -53,7 +53,7 @@ struct RhsArgs {
   const uint8_t* __restrict__ nbtab;
   int64_t E, Epad;
   int ntiles;
-  int dma;  // q is 16-byte aligned: the LDS DMA staging kernel may be used
+  int dma;  // q is 16-byte aligned and the launch configuration asks for the LDS DMA staging
   double gamma, a, b, dt;
   unsigned* flags;  // device failure flags (non-finite output)
 };
@@ -272,7 +272,7 @@ dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, do
   A.E = m.E;
   A.Epad = m.Epad;
   A.ntiles = static_cast<int>(m.Epad / 16);
-  A.dma = (reinterpret_cast<uintptr_t>(q) & 15u) == 0 ? 1 : 0;
+  A.dma = (reinterpret_cast<uintptr_t>(q) & 15u) == 0 && m.launch[DG_FP64].lds_stage ? 1 : 0;
   A.gamma = gamma;
   A.a = a;
   A.b = b;

@@ -47,7 +47,7 @@ template <int P, int MODE, int W>
 void launch_lowp_pw(const Mesh& m, const LowArgs& args, bool fused, hipStream_t s) {
   const int blocks = static_cast<int>((m.Epad / 16 + W - 1) / W);
   constexpr bool kDma = LCfg<P>::NP % 4 == 0 && MODE == 1;
-  const bool dma = kDma && (reinterpret_cast<uintptr_t>(args.q) & 15u) == 0;
+  const bool dma = kDma && (reinterpret_cast<uintptr_t>(args.q) & 15u) == 0 && m.launch[MODE].lds_stage;
   if (dma) {
     if (fused)
       rhs_euler_lowp_kernel<P, MODE, true, W, kDma><<<blocks, 64 * W, 0, s>>>(args);

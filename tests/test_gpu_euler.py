@@ -10,6 +10,7 @@ the same worst case as one side).  For every field that is not a
 near-cancellation (max|rhs_f| >= 1e-2 max T_f, where K u T <= 1e-12 max|rhs|
 holds) also max|gpu - oracle| <= 1e-12 max|rhs_f|.  Summation order
 differs between the two sides, so bit equality is not expected."""
+import itertools
 import math
 
 import numpy as np
@@ -263,7 +264,8 @@ def test_error_paths():
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_launch_configurations_give_the_same_bits(p):
     """Every launch configuration (2 or 4 tiles per block; fused or unfused
-    Runge-Kutta stages) of every contraction precision gives bitwise the
+    Runge-Kutta stages; LDS DMA or register staging of the state tile) of
+    every contraction precision gives bitwise the
     right-hand side and the steps of the initial one, on a ragged mesh with
     jumping traces."""
     dev = _dev()
@@ -273,22 +275,21 @@ def test_launch_configurations_give_the_same_bits(p):
     q0 = torch.from_numpy(np.ascontiguousarray(q_np)).to(dev)
     dt = 0.2 * oe.cfl_dt(c["ops"], c["geo"], q_np, 1.0)
     for mode in ("fp64", "fp32", "split_bf16"):
-        assert mesh.get_launch(mode) == dict(waves_per_block=4, rk_fused=1)
+        assert mesh.get_launch(mode) == dict(waves_per_block=4, rk_fused=1, lds_stage=1)
         ref_rhs, ref_q = None, None
-        for w in (4, 2):
-            for fused in (1, 0):
-                mesh.set_launch(mode, w, fused)
-                out = torch.empty_like(q0)
-                dg.rhs(mesh, q0, out, mode)
-                q = q0.clone()
-                work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
-                for s in range(2):
-                    dg.rk_step(mesh, q, work, s * dt, dt, mode)
-                torch.cuda.synchronize()
-                if ref_rhs is None:
-                    ref_rhs, ref_q = out.clone(), q.clone()
-                assert torch.equal(out, ref_rhs), f"{mode} rhs waves={w}"
-                assert torch.equal(q, ref_q), f"{mode} rk waves={w} fused={fused}"
+        for w, fused, lds in itertools.product((4, 2), (1, 0), (1, 0)):
+            mesh.set_launch(mode, w, fused, lds)
+            out = torch.empty_like(q0)
+            dg.rhs(mesh, q0, out, mode)
+            q = q0.clone()
+            work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
+            for s in range(2):
+                dg.rk_step(mesh, q, work, s * dt, dt, mode)
+            torch.cuda.synchronize()
+            if ref_rhs is None:
+                ref_rhs, ref_q = out.clone(), q.clone()
+            assert torch.equal(out, ref_rhs), f"{mode} rhs waves={w} lds={lds}"
+            assert torch.equal(q, ref_q), f"{mode} rk waves={w} fused={fused} lds={lds}"
         mesh.set_launch(mode, 4, 1)
 
 
@@ -299,8 +300,8 @@ def test_autotune_chooses_sets_and_caches(tmp_path):
     cache = tmp_path / "tune.json"
     cfg, ms = mesh.autotune("split_bf16", cache_path=cache, trials=2)
     assert ms > 0 and cfg == mesh.get_launch("split_bf16")
-    assert cfg["waves_per_block"] in (2, 4) and cfg["rk_fused"] in (0, 1)
-    assert mesh.get_launch("fp64") == dict(waves_per_block=4, rk_fused=1)  # other precisions untouched
+    assert cfg["waves_per_block"] in (2, 4) and cfg["rk_fused"] in (0, 1) and cfg["lds_stage"] in (0, 1)
+    assert mesh.get_launch("fp64") == dict(waves_per_block=4, rk_fused=1, lds_stage=1)  # other precisions untouched
     import json
     (key, entry), = json.loads(cache.read_text())["entries"].items()
     assert "split_bf16" in key and ":p3:" in key and f":E{mesh.E}" in key
