@@ -280,4 +280,60 @@ __device__ inline void store_tile(const double* sq, int nval, int64_t base, int6
   raise_flag(flags, bad, kFlagNonFinite);
 }
 
+// This lane's entries (64 k + lane, k < ceil(TQ / 64)) of each field of the
+// state tile staged in LDS, read back into registers before the tile buffer is
+// reused for the outputs: the fused Runge-Kutta stage takes q from here
+// instead of reading it from memory a second time.  Entries at or past nval
+// repeat the last valid one (they are never stored).
+template <int TQ>
+__device__ inline void tile_from_lds(const double* sq, int nval, int lane, double v[5][(TQ + 63) / 64]) {
+  constexpr int KN = (TQ + 63) / 64;
+#pragma unroll
+  for (int f = 0; f < 5; ++f)
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+      const int i = 64 * k + lane;
+      v[f][k] = sq[f * TQ + (i < nval ? i : nval - 1)];
+    }
+}
+
+// store_tile's fused stage with the old state already in registers (qv from
+// tile_from_lds): only the residual is read from memory, every res value of a
+// round of fields before the round's first store.
+template <int TQ>
+__device__ inline void store_tile_stage(const double* sq, const double qv[5][(TQ + 63) / 64], int nval, int64_t base,
+                                        int64_t Es, int lane, const double* res_in, double* res, double* qout, double a,
+                                        double b, double dt, unsigned* flags) {
+  constexpr int KN = (TQ + 63) / 64;
+  constexpr int FG = tile_round_fields<TQ>();
+  {
+    int lo = static_cast<int>(base), hi = static_cast<int>(base >> 32);
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    base = (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
+  }
+  bool bad = false;
+#pragma unroll
+  for (int f0 = 0; f0 < 5; f0 += FG) {
+    double rv[FG][KN];
+#pragma unroll
+    for (int ff = 0; ff < FG; ++ff)
+#pragma unroll
+      for (int k = 0; k < KN; ++k) {
+        const int i = 64 * k + lane;
+        const int64_t idx = (f0 + ff) * Es + base + (i < nval ? i : nval - 1);  // clamped: unconditional loads
+        rv[ff][k] = f0 + ff < 5 && a != 0.0 ? res_in[idx] : 0.0;
+      }
+#pragma unroll
+    for (int ff = 0; ff < FG; ++ff)
+#pragma unroll
+      for (int k = 0; k < KN; ++k) {
+        const int i = 64 * k + lane;
+        if (f0 + ff < 5 && i < nval)
+          bad |= nonfinite(stage_store((f0 + ff) * Es + base + i, sq[(f0 + ff) * TQ + i], rv[ff][k], qv[f0 + ff][k], res,
+                                       qout, a, b, dt));
+      }
+  }
+  raise_flag(flags, bad, kFlagNonFinite);
+}
+
 }  // namespace dg

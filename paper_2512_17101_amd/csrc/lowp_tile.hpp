@@ -330,9 +330,13 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
       return 16 * rb + 4 * g + v;
     };
     if constexpr (STAGED) {
-      // through the LDS tile buffer (the state is no longer needed there):
-      // coalesced stores, and in the fused stage all res / q loads of a
-      // round in flight together
+      // through the LDS tile buffer (the state is no longer needed there;
+      // the fused stage first takes its share of it into registers):
+      // coalesced stores, and in the fused stage all res loads of a round in
+      // flight together
+      constexpr int KN = (TQ + 63) / 64;
+      double qv[FUSED ? 5 : 1][FUSED ? KN : 1];
+      if constexpr (FUSED) tile_from_lds<TQ>(sq, nval, lane, qv);
       __builtin_amdgcn_wave_barrier();
       if (valid) {
 #pragma unroll
@@ -346,7 +350,11 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
             }
       }
       __builtin_amdgcn_wave_barrier();
-      store_tile<FUSED, TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res_in, A.res, A.qout, q, A.a, A.b, A.dt, A.flags);
+      if constexpr (FUSED)
+        store_tile_stage<TQ>(sq, qv, nval, e0 * C::NP, Es, lane, A.res_in, A.res, A.qout, A.a, A.b, A.dt, A.flags);
+      else
+        store_tile<false, TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res_in, A.res, A.qout, q, A.a, A.b, A.dt,
+                              A.flags);
     } else if constexpr (!FUSED) {
       if (valid) {
         bool bad = false;

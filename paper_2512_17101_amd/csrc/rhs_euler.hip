@@ -19,7 +19,8 @@
 //   Delta = 1/2 (N.F(q-) - N.F(q+)) - 1/2 max(|U_n-| + c- |N|, |U_n+| + c+ |N|) (q- - q+).
 // Fused Runge-Kutta epilogue (stage of the 2N-storage scheme):
 //   res <- a res + dt rhs;  q_out <- q + b res   (q_out is a second buffer,
-//   because neighbouring tiles still read q).
+//   because neighbouring tiles still read q; the tile's q comes from its
+//   LDS copy, not from memory).
 #include "euler_point.hpp"
 #include "internal.hpp"
 
@@ -205,9 +206,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ?
   }
 
   // ---- store through this wave's LDS tile buffer (the state is no longer
-  // needed there): lane (n, g) holds rows 16 rb + 4 v + g and 16 NB16 + 4 rb4 + g
+  // needed there; the fused stage first takes its share of it into
+  // registers): lane (n, g) holds rows 16 rb + 4 v + g and 16 NB16 + 4 rb4 + g
   // of element n; the tile's outputs of one field are contiguous in memory,
   // so they leave with coalesced stores.
+  constexpr int KN = (TL::TQ + 63) / 64;
+  double qv[FUSED ? 5 : 1][FUSED ? KN : 1];
+  if constexpr (FUSED) tile_from_lds<TL::TQ>(sq, nval, lane, qv);
   __builtin_amdgcn_wave_barrier();
   if (valid) {
 #pragma unroll
@@ -224,7 +229,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ?
     }
   }
   __builtin_amdgcn_wave_barrier();
-  store_tile<FUSED, TL::TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res_in, A.res, A.qout, q, A.a, A.b, A.dt, A.flags);
+  if constexpr (FUSED)
+    store_tile_stage<TL::TQ>(sq, qv, nval, e0 * C::NP, Es, lane, A.res_in, A.res, A.qout, A.a, A.b, A.dt, A.flags);
+  else
+    store_tile<false, TL::TQ>(sq, nval, e0 * C::NP, Es, lane, A.rhs, A.res_in, A.res, A.qout, q, A.a, A.b, A.dt,
+                              A.flags);
 }
 
 template <int P, int W>
