@@ -225,47 +225,19 @@ __global__ __launch_bounds__(256) void ns_grad_kernel(NsArgs A) {
   for (int k = tid; k < nval; k += blockDim.x) dst[k] = s_buf[k];
 }
 
-// Face jump of one face node (element ef, face node fm):
-//   Delta = 1/2 (N.F(-) - N.F(+)) - 1/2 max(|U_N-| + c- |N|, |U_N+| + c+ |N|) (q- - q+),
-// F the total flux, N = Fscale n.
-template <int P>
-__device__ inline void ns_face_jump(const NsArgs& A, int64_t Es, int64_t ef, int fm, int2 cn, int own,
-                                    const double gm[9], double D[kNsFields]) {
-  using C = NsCfg<P>;
-  const int face = fm / C::NFP, mm = fm - face * C::NFP;
-  const int jp = A.nbtab[(face * 24 + cn.y) * C::NFP + mm];
-  double N[3];
-  scaled_normal(face, gm, N[0], N[1], N[2]);
-  const double Fs = sqrt_pos(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
-  const Transport tr{A.mu, A.Pr, A.Sc};
-  double qm[kNsFields], Fm[kNsFields];
-  double Unm, cm;
-  {
-    const int64_t im = ef * C::NP + own;
-    double s[3 * kNsPrims];
-    load_state(A.q, Es, im, qm);
-    load_sigma(A.sigma, im, s);
-    NsNode nd;
-    ns_node(A.th, qm, A.T[im], s, nd);
-    Unm = ns_flux_along(tr, nd, qm, s, N, Fm);
-    cm = nd.c;
-  }
-  const int64_t ip = static_cast<int64_t>(cn.x) * C::NP + jp;
-  double qp[kNsFields], Fp[kNsFields], s[3 * kNsPrims];
-  load_state(A.q, Es, ip, qp);
-  load_sigma(A.sigma, ip, s);
-  NsNode nd;
-  ns_node(A.th, qp, A.T[ip], s, nd);
-  const double Unp = ns_flux_along(tr, nd, qp, s, N, Fp);
-  const double lamFs = fmax(fabs(Unm) + cm * Fs, fabs(Unp) + nd.c * Fs);
-#pragma unroll
-  for (int f = 0; f < kNsFields; ++f) D[f] = 0.5 * (Fm[f] - Fp[f]) - 0.5 * lamFs * (qm[f] - qp[f]);
-}
-
-// Right-hand side: block of EPB_R = 256 / (4 Nfp) elements; thread s < EPB_R 4 Nfp
-// forms the jump of face node s, thread t < EPB_R Np the contravariant fluxes
-// of volume node t, both straight into LDS; then the 12 fields' contractions
-// are split over H = 256 / (EPB_R Np) thread sets of EPB_R Np threads.
+// Right-hand side: block of EPB = 256 / (4 Nfp) elements.
+//  1. Thread t < EPB Np evaluates volume node t once: the contravariant total
+//     fluxes G_a (a = r, s, t) of the 12 fields go to LDS, and so does its
+//     sound speed.  Thread s < EPB 4 Nfp evaluates the neighbour node of face
+//     node s: its total flux along the face's scaled normal N, its normal
+//     velocity and sound speed, kept in registers with its state.
+//  2. After the block barrier, face node s forms its own side from LDS: with
+//     N = sum_a c_a grad a (c_a in {0, +-1}), N . F(-) = sum_a c_a G_a of the
+//     own volume node, which is not evaluated again.  Then the jump
+//       Delta = 1/2 (N.F(-) - N.F(+)) - 1/2 max(|U_N-| + c- |N|, |U_N+| + c+ |N|) (q- - q+)
+//     goes to LDS.
+//  3. The contractions of the 12 fields are split over H = 256 / (EPB Np)
+//     thread sets of EPB Np threads.
 template <int P>
 struct NsRhsCfg {
   using C = NsCfg<P>;
@@ -283,27 +255,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
   __shared__ double s_op[C::KOP * C::NP];
   __shared__ double s_G[R::EPB][kNsFields][3][C::NP];
   __shared__ double s_D[R::EPB][kNsFields][C::NFN];
+  __shared__ double s_c[R::EPB][C::NP];
   const int tid = threadIdx.x;
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * R::EPB;
   const int64_t Es = A.E * C::NP;
   const Transport tr{A.mu, A.Pr, A.Sc};
 
-  // the face node's connectivity, mask and metric are requested first, so
-  // they arrive while this thread's volume node is evaluated
+  // face node of this thread (clamped indices; results of threads without
+  // one, or of elements past the mesh, are discarded)
   const bool fnode = tid < R::EPB * C::NFN;
-  int2 fcn;
-  int fown;
+  const int fs = fnode ? tid : 0;
+  const int fl = fs / C::NFN, fm = fs - fl * C::NFN;
+  const int face = fm / C::NFP, mm = fm - face * C::NFP;
+  const int64_t ef = e0 + fl < A.E ? e0 + fl : A.E - 1;
+  const int2 fcn = A.conn[face * A.Epad + ef];
+  const int fown = A.fmask[fm];
+  const int jp = A.nbtab[(face * 24 + fcn.y) * C::NFP + mm];
   double fgm[9];
-  {
-    const int s = fnode ? tid : 0;
-    const int fl = s / C::NFN, fm = s - fl * C::NFN;
-    const int64_t ef = e0 + fl < A.E ? e0 + fl : A.E - 1;
-    fcn = A.conn[(fm / C::NFP) * A.Epad + ef];
-    fown = A.fmask[fm];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) fgm[k] = A.geo[k * A.Epad + ef];
-  }
+  for (int k = 0; k < 9; ++k) fgm[k] = A.geo[k * A.Epad + ef];
   stage_block_array<C::KOP * C::NP, 256>(s_op, A.opT, tid);
+
   if (tid < R::NV) {  // one volume node
     const int el = tid / C::NP, i = tid - el * C::NP;
     const int64_t e = e0 + el;
@@ -323,19 +295,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
 #pragma unroll
         for (int f = 0; f < kNsFields; ++f) s_G[el][f][a][i] = G[f];
       }
+      s_c[el][i] = nd.c;
     } else {
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int f = 0; f < kNsFields; ++f) s_G[el][f][a][i] = 0.0;
+      s_c[el][i] = 0.0;
     }
   }
-  if (fnode) {  // one face node
-    const int fl = tid / C::NFN, fm = tid - fl * C::NFN;
-    const int64_t ef = e0 + fl;
+
+  // the neighbour side of this thread's face node, and its own state
+  double N[3];
+  scaled_normal(face, fgm, N[0], N[1], N[2]);
+  double qp[kNsFields], Fp[kNsFields], qm[kNsFields];
+  double Unp, cp;
+  {
+    const int64_t ip = static_cast<int64_t>(fcn.x) * C::NP + jp;
+    double sg[3 * kNsPrims];
+    load_state(A.q, Es, ip, qp);
+    load_sigma(A.sigma, ip, sg);
+    load_state(A.q, Es, ef * C::NP + fown, qm);
+    NsNode nd;
+    ns_node(A.th, qp, A.T[ip], sg, nd);
+    Unp = ns_flux_along(tr, nd, qp, sg, N, Fp);
+    cp = nd.c;
+  }
+  __syncthreads();
+  if (fnode) {
     double D[kNsFields];
-    if (ef < A.E) {
-      ns_face_jump<P>(A, Es, ef, fm, fcn, fown, fgm, D);
+    if (e0 + fl < A.E) {
+      // N = c_r grad r + c_s grad s + c_t grad t for this face (as scaled_normal)
+      const int hi = face >> 1, lo = face & 1;
+      const double cr = static_cast<double>(hi * (1 - 2 * lo));
+      const double cs = static_cast<double>((lo ^ hi) * (2 * hi - 1));
+      const double ct = static_cast<double>((1 - lo) * (2 * hi - 1));
+      const double Fs = sqrt_pos(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+      const double ir = recip(qm[0]);
+      const double Unm = (N[0] * qm[1] + N[1] * qm[2] + N[2] * qm[3]) * ir;
+      const double lamFs = fmax(fabs(Unm) + s_c[fl][fown] * Fs, fabs(Unp) + cp * Fs);
+#pragma unroll
+      for (int f = 0; f < kNsFields; ++f) {
+        const double Fm = cr * s_G[fl][f][0][fown] + cs * s_G[fl][f][1][fown] + ct * s_G[fl][f][2][fown];
+        D[f] = 0.5 * (Fm - Fp[f]) - 0.5 * lamFs * (qm[f] - qp[f]);
+      }
     } else {
 #pragma unroll
       for (int f = 0; f < kNsFields; ++f) D[f] = 0.0;
