@@ -26,6 +26,7 @@
 // then each node's three line derivatives and six lift terms, and (D) the
 // field's coalesced store, or the fused Runge-Kutta stage update
 // res <- a res + dt rhs, q_out <- q + b res.
+#include "euler_point.hpp"
 #include "hex.hpp"
 
 namespace dg {
@@ -64,9 +65,14 @@ template <int N1>
 __device__ inline int nidx(int a, int b, int c) { return a + N1 * (b + N1 * c); }
 
 // flux component along direction d of the five conserved fields, with the
-// velocity component u_d and the sound speed
+// velocity component u_d and the sound speed.  EXACT: correctly rounded
+// division and square root (the artificial-viscosity form, whose limiter,
+// viscosity ramp and wave-speed maximum amplify rounding across strong
+// jumps); otherwise the hardware reciprocal and reciprocal root refined by
+// two Newton steps each (within an ulp or two, at half the instructions).
+template <bool EXACT>
 __device__ inline void dir_flux(const double q[5], int d, double gamma, double F[5], double& ud, double& c) {
-  const double ir = 1.0 / q[0];
+  const double ir = EXACT ? 1.0 / q[0] : recip(q[0]);
   const double u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
   const double p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * u + q[2] * v + q[3] * w));
   ud = d == 0 ? u : d == 1 ? v : w;
@@ -76,7 +82,8 @@ __device__ inline void dir_flux(const double q[5], int d, double gamma, double F
   F[3] = q[3] * ud;
   F[1 + d] += p;
   F[4] = (q[4] + p) * ud;
-  c = sqrt(gamma * p * ir);
+  const double c2 = gamma * p * ir;
+  c = EXACT || !(c2 > 0.0) ? sqrt(c2) : sqrt_pos(c2);  // (c2 <= 0 or NaN: the IEEE root, 0 or NaN)
 }
 
 template <int P, bool FUSED, bool AV>
@@ -160,8 +167,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
 #pragma unroll
       for (int f = 0; f < 5; ++f) qm[f] = s_q[fl][f][ownn[u]];
       double FM[5], FP[5], uM, cM, uP, cP;
-      dir_flux(qm, d, A.gamma, FM, uM, cM);
-      dir_flux(qp[u], d, A.gamma, FP, uP, cP);
+      dir_flux<AV>(qm, d, A.gamma, FM, uM, cM);
+      dir_flux<AV>(qp[u], d, A.gamma, FP, uP, cP);
       const double lam = fmax(fabs(uM) + cM, fabs(uP) + cP);
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
   const int cx = e % A.nx, cxy = e / A.nx;
   const double ihx = A.ih[cx], ihy = A.ih[A.nx + cxy % A.ny], ihz = A.ih[A.nx + A.ny + cxy / A.ny];
   const int a = ic % N1, bb = (ic / N1) % N1, c = ic / (N1 * N1);
-  const double ir = 1.0 / q0;
+  const double ir = AV ? 1.0 / q0 : recip(q0);
   const double vx = q1 * ir, vy = q2 * ir, vz = q3 * ir;
   const double pr = (A.gamma - 1.0) * (q4 - 0.5 * (q1 * vx + q2 * vy + q3 * vz));
   const int base = elc * NP;
@@ -244,6 +251,236 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
   raise_flag(A.flags, bad, kFlagNonFinite);
 }
 
+// Tiled form (no artificial viscosity): a 256-thread block owns a box of
+// TX x TY x TZ cells, one thread per node, so most face neighbours are in
+// the block.  Each face node of the tile (every cell face in the box,
+// including the planes on its boundary) is evaluated once for both sides:
+// with L, R the cells before and after it along d,
+//   A = 1/2 (F_d(q_L) - F_d(q_R)),  B = 1/2 max(|u_L| + c_L, |u_R| + c_R) (q_L - q_R),
+// L's jump on its +d face is A - B and R's on its -d face is A + B (the
+// form above with the signs of n_d worked out).  A side inside the tile
+// (and inside the grid) comes from the tile's LDS copy; the others, on the
+// tile's boundary planes or past a ragged grid end, are read from memory
+// with the periodic wrap.  Own state and output move in runs of TX cells
+// (TX Np consecutive doubles per field).
+// tile of the p = 1 kernel: 4 x 4 x 2 cells of 8 nodes
+constexpr int kTileX1 = 4, kTileY1 = 4, kTileZ1 = 2;
+
+template <int P, int TX, int TY, int TZ>
+struct HexTileCfg {
+  static constexpr int N1 = P + 1;
+  static constexpr int NP = N1 * N1 * N1;
+  static constexpr int NFP = N1 * N1;
+  static constexpr int NC = TX * TY * TZ;  // cells of the tile
+  static constexpr int NT = NC * NP;       // threads owning a node
+  static constexpr int NSX = (TX + 1) * TY * TZ * NFP;
+  static constexpr int NSY = TX * (TY + 1) * TZ * NFP;
+  static constexpr int NSZ = TX * TY * (TZ + 1) * NFP;
+  static constexpr int NS = NSX + NSY + NSZ;  // face nodes of the tile
+  static constexpr int KF = (NS + 255) / 256;
+  static_assert(NT <= 256, "one thread per node");
+};
+
+// wraps a cell coordinate into [0, n) (it lies in [-n, 2 n + T))
+__device__ inline int wrap_cell(int c, int n) {
+  c = c < 0 ? c + n : c;
+  while (c >= n) c -= n;
+  return c;
+}
+
+template <int P, int TX, int TY, int TZ, bool FUSED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void hex_rhs_tile_kernel(HexArgs A) {
+  static_assert(P == 1, "line partners by lane exchange: a cell's 8 nodes are 8 consecutive lanes");
+  using C = HexTileCfg<P, TX, TY, TZ>;
+  constexpr int N1 = C::N1, NP = C::NP, NFP = C::NFP, NC = C::NC;
+  __shared__ double s_q[NC][5][NP];
+  __shared__ double s_D[NC][6][5][NFP];
+  const int tid = threadIdx.x;
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+  const int X0 = (blockIdx.x % ntx) * TX, Y0 = ((blockIdx.x / ntx) % nty) * TY, Z0 = (blockIdx.x / (ntx * nty)) * TZ;
+  const size_t Es = static_cast<size_t>(A.E) * NP;  // E Np < 2^31 (checked on the host)
+
+  // this thread's node: cell (lx, ly, lz) of the tile, node i
+  const bool own = tid < C::NT;
+  const int cl = own ? tid / NP : 0, ic = own ? tid - (tid / NP) * NP : 0;
+  const int lx = cl % TX, ly = (cl / TX) % TY, lz = cl / (TX * TY);
+  const bool valid = own && X0 + lx < nx && Y0 + ly < ny && Z0 + lz < nz;
+  const int gx = valid ? X0 + lx : 0, gy = valid ? Y0 + ly : 0, gz = valid ? Z0 + lz : 0;
+  const int e = gx + nx * (gy + ny * gz);
+  const int idx = e * NP + ic;
+
+  // (A) every global read first: the operator, the own node, and the sides
+  // of this thread's face nodes that lie outside the tile
+  double D1[N1 * N1], lift[2 * N1];  // the 1-D tables (wave-uniform)
+#pragma unroll
+  for (int j = 0; j < N1 * N1; ++j) D1[j] = A.op[j];
+#pragma unroll
+  for (int j = 0; j < 2 * N1; ++j) lift[j] = A.op[N1 * N1 + j];
+  double qv[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) qv[f] = A.q[f * Es + idx];
+  // face node u of this thread: direction, the two cells (tile-local
+  // coordinates, -1 / T for outside), node indices, which sides are in the
+  // tile, and the out-of-tile sides' states
+  int fdir[C::KF], fcell[C::KF][2], fm[C::KF];
+  bool fin[C::KF][2], fuse[C::KF];
+  double gq[C::KF][2][5];
+#pragma unroll
+  for (int u = 0; u < C::KF; ++u) {
+    const int s = tid + 256 * u < C::NS ? tid + 256 * u : C::NS - 1;
+    int d, k, t1, t2, r;
+    if (s < C::NSX) {
+      d = 0; r = s;
+    } else if (s < C::NSX + C::NSY) {
+      d = 1; r = s - C::NSX;
+    } else {
+      d = 2; r = s - C::NSX - C::NSY;
+    }
+    const int m = r % NFP;
+    r /= NFP;
+    const int Td = d == 0 ? TX : d == 1 ? TY : TZ;
+    const int T1 = d == 0 ? TY : TX;  // first transverse extent (y for x faces, else x)
+    k = r % (Td + 1);
+    r /= Td + 1;
+    t1 = r % T1;
+    t2 = r / T1;
+    // tile-local cells of both sides: (x, y, z) with the d coordinate k - 1 (L) or k (R)
+    int cc[2][3];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int kd = k - 1 + side;
+      cc[side][0] = d == 0 ? kd : t1;
+      cc[side][1] = d == 0 ? t1 : (d == 1 ? kd : t2);
+      cc[side][2] = d == 2 ? kd : t2;
+    }
+    const int n_d = d == 0 ? nx : d == 1 ? ny : nz;
+    const int O_d = d == 0 ? X0 : d == 1 ? Y0 : Z0;
+    // transverse cells inside the grid (else no valid cell touches this face)
+    const bool trans_ok = (d == 0 ? (Y0 + t1 < ny && Z0 + t2 < nz)
+                                  : d == 1 ? (X0 + t1 < nx && Z0 + t2 < nz) : (X0 + t1 < nx && Y0 + t2 < ny));
+    const int uu = m % N1, vv = m / N1;
+    fdir[u] = d;
+    fm[u] = m;
+    bool any = false;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int kd = k - 1 + side;
+      const bool inside = s == tid + 256 * u && trans_ok && kd >= 0 && kd < Td && O_d + kd < n_d;
+      fin[u][side] = inside;
+      fcell[u][side] = cc[side][0] + TX * (cc[side][1] + TY * cc[side][2]);
+      any |= inside;
+      // the side's node: position P (L, its +d face) or 0 (R, its -d face) along d
+      const int pd = side ? 0 : P;
+      const int nn = d == 0 ? nidx<N1>(pd, uu, vv) : d == 1 ? nidx<N1>(uu, pd, vv) : nidx<N1>(uu, vv, pd);
+      // global cell of the side (periodic), read when it is not in the tile
+      int g3[3] = {X0 + cc[side][0], Y0 + cc[side][1], Z0 + cc[side][2]};
+      g3[d] = wrap_cell(O_d + kd, n_d);
+      const int ge = trans_ok ? g3[0] + nx * (g3[1] + ny * g3[2]) : 0;
+      const int gi = ge * NP + nn;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) gq[u][side][f] = inside ? 0.0 : A.q[f * Es + gi];
+    }
+    fuse[u] = any;
+  }
+  if (own) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) s_q[cl][f][ic] = qv[f];
+  }
+  __syncthreads();
+
+  // (B) jumps of the tile's face nodes, both sides at once
+#pragma unroll
+  for (int u = 0; u < C::KF; ++u) {
+    if (!fuse[u]) continue;
+    const int d = fdir[u], m = fm[u];
+    const int uu = m % N1, vv = m / N1;
+    double qs[2][5];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int pd = side ? 0 : P;
+      const int nn = d == 0 ? nidx<N1>(pd, uu, vv) : d == 1 ? nidx<N1>(uu, pd, vv) : nidx<N1>(uu, vv, pd);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) qs[side][f] = fin[u][side] ? s_q[fcell[u][side]][f][nn] : gq[u][side][f];
+    }
+    double FL[5], FR[5], uL, cL, uR, cR;
+    dir_flux<false>(qs[0], d, A.gamma, FL, uL, cL);
+    dir_flux<false>(qs[1], d, A.gamma, FR, uR, cR);
+    const double lam = fmax(fabs(uL) + cL, fabs(uR) + cR);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const double a = 0.5 * (FL[f] - FR[f]);
+      const double b = 0.5 * lam * (qs[0][f] - qs[1][f]);
+      if (fin[u][0]) s_D[fcell[u][0]][2 * d + 1][f][m] = a - b;
+      if (fin[u][1]) s_D[fcell[u][1]][2 * d][f][m] = a + b;
+    }
+  }
+
+  __syncthreads();  // the jumps are written
+
+  // (C) per field: the own node's three fluxes; the line partner's (node
+  // i ^ 1, i ^ 2, i ^ 4 along x, y, z: lane tid ^ 1, 2, 4 of the same cell)
+  // by lane exchange; the line derivatives and the lift; (D) the field's
+  // store or stage update (as in hex_rhs_kernel)
+  const double q0 = qv[0], q1 = qv[1], q2 = qv[2], q3 = qv[3], q4 = qv[4];
+  double rv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (FUSED && A.a != 0.0) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) rv[f] = A.res_in[f * Es + idx];
+  }
+  const double ihx = A.ih[gx], ihy = A.ih[nx + gy], ihz = A.ih[nx + ny + gz];
+  const int a = ic & 1, bb = (ic >> 1) & 1, c = ic >> 2;
+  // this node's rows of D1 and lift along x, y, z (selected, not indexed:
+  // an array indexed by a lane value would live in scratch memory)
+  const double dxr0 = a ? D1[2] : D1[0], dxr1 = a ? D1[3] : D1[1];
+  const double dyr0 = bb ? D1[2] : D1[0], dyr1 = bb ? D1[3] : D1[1];
+  const double dzr0 = c ? D1[2] : D1[0], dzr1 = c ? D1[3] : D1[1];
+  const double lxr0 = a ? lift[2] : lift[0], lxr1 = a ? lift[3] : lift[1];
+  const double lyr0 = bb ? lift[2] : lift[0], lyr1 = bb ? lift[3] : lift[1];
+  const double lzr0 = c ? lift[2] : lift[0], lzr1 = c ? lift[3] : lift[1];
+  const double ir = recip(q0);
+  const double vx = q1 * ir, vy = q2 * ir, vz = q3 * ir;
+  const double pr = (A.gamma - 1.0) * (q4 - 0.5 * (q1 * vx + q2 * vy + q3 * vz));
+  bool bad = false;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double qf = qv[f];
+    const double qe = f == 4 ? qf + pr : qf;
+    const double fx = qe * vx + (f == 1 ? pr : 0.0);
+    const double fy = qe * vy + (f == 2 ? pr : 0.0);
+    const double fz = qe * vz + (f == 3 ? pr : 0.0);
+    const double px = __shfl_xor(fx, 1, 64), py = __shfl_xor(fy, 2, 64), pz = __shfl_xor(fz, 4, 64);
+    // F at line positions 0 and 1 of this node's x, y, z lines
+    const double x0 = a ? px : fx, x1 = a ? fx : px;
+    const double y0 = bb ? py : fy, y1 = bb ? fy : py;
+    const double z0 = c ? pz : fz, z1 = c ? fz : pz;
+    double dx = 0.0, dy = 0.0, dz = 0.0;
+    dx = fma(dxr0, x0, dx);
+    dy = fma(dyr0, y0, dy);
+    dz = fma(dzr0, z0, dz);
+    dx = fma(dxr1, x1, dx);
+    dy = fma(dyr1, y1, dy);
+    dz = fma(dzr1, z1, dz);
+    const double lx2 = lxr0 * s_D[cl][0][f][bb + N1 * c] + lxr1 * s_D[cl][1][f][bb + N1 * c];
+    const double ly2 = lyr0 * s_D[cl][2][f][a + N1 * c] + lyr1 * s_D[cl][3][f][a + N1 * c];
+    const double lz2 = lzr0 * s_D[cl][4][f][a + N1 * bb] + lzr1 * s_D[cl][5][f][a + N1 * bb];
+    const double out = ihx * (lx2 - dx) + ihy * (ly2 - dy) + ihz * (lz2 - dz);
+    if (valid) {
+      if (FUSED) {
+        const double rn = (A.a == 0.0 ? 0.0 : A.a * rv[f]) + A.dt * out;
+        const double qn = qf + A.b * rn;
+        if (A.res) A.res[f * Es + idx] = rn;
+        A.qout[f * Es + idx] = qn;
+        bad |= nonfinite(qn);
+      } else {
+        A.rhs[f * Es + idx] = out;
+        bad |= nonfinite(out);
+      }
+    }
+  }
+  raise_flag(A.flags, bad, kFlagNonFinite);
+}
+
 template <int P>
 dg_status launch_p(const HexMesh& m, const HexArgs& A, bool fused, hipStream_t s) {
   using C = HexCfg<P>;
@@ -253,6 +490,15 @@ dg_status launch_p(const HexMesh& m, const HexArgs& A, bool fused, hipStream_t s
       hipLaunchKernelGGL((hex_rhs_kernel<P, true, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
     else
       hipLaunchKernelGGL((hex_rhs_kernel<P, false, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+  } else if (P == 1) {
+    const int64_t tiles = static_cast<int64_t>((m.nx + kTileX1 - 1) / kTileX1) * ((m.ny + kTileY1 - 1) / kTileY1) *
+                          ((m.nz + kTileZ1 - 1) / kTileZ1);
+    if (fused)
+      hipLaunchKernelGGL((hex_rhs_tile_kernel<1, kTileX1, kTileY1, kTileZ1, true>), dim3(static_cast<unsigned>(tiles)),
+                         dim3(256), 0, s, A);
+    else
+      hipLaunchKernelGGL((hex_rhs_tile_kernel<1, kTileX1, kTileY1, kTileZ1, false>),
+                         dim3(static_cast<unsigned>(tiles)), dim3(256), 0, s, A);
   } else if (fused) {
     hipLaunchKernelGGL((hex_rhs_kernel<P, true, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
   } else {
