@@ -251,14 +251,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
   raise_flag(A.flags, bad, kFlagNonFinite);
 }
 
-// Tiled form (no artificial viscosity): a 256-thread block owns a box of
-// TX x TY x TZ cells, one thread per node, so most face neighbours are in
+// Tiled form for p = 1, with or without artificial viscosity: a 256-thread
+// block owns a box of TX x TY x TZ cells, one thread per node, so most face neighbours are in
 // the block.  Each face node of the tile (every cell face in the box,
 // including the planes on its boundary) is evaluated once for both sides:
 // with L, R the cells before and after it along d,
 //   A = 1/2 (F_d(q_L) - F_d(q_R)),  B = 1/2 max(|u_L| + c_L, |u_R| + c_R) (q_L - q_R),
 // L's jump on its +d face is A - B and R's on its -d face is A + B (the
-// form above with the signs of n_d worked out).  A side inside the tile
+// form above with the signs of n_d worked out; with viscosity both add the
+// central viscous term (G_d(R) - G_d(L)) / 2).  A side inside the tile
 // (and inside the grid) comes from the tile's LDS copy; the others, on the
 // tile's boundary planes or past a ragged grid end, are read from memory
 // with the periodic wrap.  Own state and output move in runs of TX cells
@@ -288,7 +289,7 @@ __device__ inline int wrap_cell(int c, int n) {
   return c;
 }
 
-template <int P, int TX, int TY, int TZ, bool FUSED>
+template <int P, int TX, int TY, int TZ, bool FUSED, bool AV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void hex_rhs_tile_kernel(HexArgs A) {
   static_assert(P == 1, "line partners by lane exchange: a cell's 8 nodes are 8 consecutive lanes");
   using C = HexTileCfg<P, TX, TY, TZ>;
@@ -326,6 +327,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void h
   int fdir[C::KF], fcell[C::KF][2], fm[C::KF];
   bool fin[C::KF][2], fuse[C::KF];
   double gq[C::KF][2][5];
+  // artificial viscosity: whether each side's element is viscous, and the
+  // side's node (the G values are loaded after the barrier, rarely)
+  bool fvis[AV ? C::KF : 1][2];
+  int fgi[AV ? C::KF : 1][2];
 #pragma unroll
   for (int u = 0; u < C::KF; ++u) {
     const int s = tid + 256 * u < C::NS ? tid + 256 * u : C::NS - 1;
@@ -380,6 +385,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void h
       const int gi = ge * NP + nn;
 #pragma unroll
       for (int f = 0; f < 5; ++f) gq[u][side][f] = inside ? 0.0 : A.q[f * Es + gi];
+      if (AV) {
+        fvis[u][side] = trans_ok && A.eps[ge] > 0.0;
+        fgi[u][side] = gi;
+      }
     }
     fuse[u] = any;
   }
@@ -407,12 +416,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void h
     dir_flux<false>(qs[0], d, A.gamma, FL, uL, cL);
     dir_flux<false>(qs[1], d, A.gamma, FR, uR, cR);
     const double lam = fmax(fabs(uL) + cL, fabs(uR) + cR);
+    // with viscosity both sides add n_d ((G+ + G-)/2 - G-) = (G_R - G_L) / 2,
+    // G_d of a side being zero (and not stored) in an inviscid element
+    double gv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (AV && (fvis[u][0] || fvis[u][1])) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        const double gL = fvis[u][0] ? A.G[(d * 5 + f) * Es + fgi[u][0]] : 0.0;
+        const double gR = fvis[u][1] ? A.G[(d * 5 + f) * Es + fgi[u][1]] : 0.0;
+        gv[f] = 0.5 * gR - 0.5 * gL;
+      }
+    }
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
       const double a = 0.5 * (FL[f] - FR[f]);
       const double b = 0.5 * lam * (qs[0][f] - qs[1][f]);
-      if (fin[u][0]) s_D[fcell[u][0]][2 * d + 1][f][m] = a - b;
-      if (fin[u][1]) s_D[fcell[u][1]][2 * d][f][m] = a + b;
+      const double v = gv[f];
+      if (fin[u][0]) s_D[fcell[u][0]][2 * d + 1][f][m] = AV ? (a - b) + v : a - b;
+      if (fin[u][1]) s_D[fcell[u][1]][2 * d][f][m] = AV ? (a + b) + v : a + b;
     }
   }
 
@@ -442,13 +463,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void h
   const double vx = q1 * ir, vy = q2 * ir, vz = q3 * ir;
   const double pr = (A.gamma - 1.0) * (q4 - 0.5 * (q1 * vx + q2 * vy + q3 * vz));
   bool bad = false;
+  const bool visc_own = AV && valid && A.eps[e] > 0.0;
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     const double qf = qv[f];
     const double qe = f == 4 ? qf + pr : qf;
-    const double fx = qe * vx + (f == 1 ? pr : 0.0);
-    const double fy = qe * vy + (f == 2 ? pr : 0.0);
-    const double fz = qe * vz + (f == 3 ? pr : 0.0);
+    double fx = qe * vx + (f == 1 ? pr : 0.0);
+    double fy = qe * vy + (f == 2 ? pr : 0.0);
+    double fz = qe * vz + (f == 3 ? pr : 0.0);
+    if (AV && visc_own) {  // total flux F - G (the viscous term enters as + div G)
+      fx -= A.G[(0 * 5 + f) * Es + idx];
+      fy -= A.G[(1 * 5 + f) * Es + idx];
+      fz -= A.G[(2 * 5 + f) * Es + idx];
+    }
     const double px = __shfl_xor(fx, 1, 64), py = __shfl_xor(fy, 2, 64), pz = __shfl_xor(fz, 4, 64);
     // F at line positions 0 and 1 of this node's x, y, z lines
     const double x0 = a ? px : fx, x1 = a ? fx : px;
@@ -485,20 +512,25 @@ template <int P>
 dg_status launch_p(const HexMesh& m, const HexArgs& A, bool fused, hipStream_t s) {
   using C = HexCfg<P>;
   const int64_t blocks = (m.E + C::EPB - 1) / C::EPB;
-  if (A.G) {
+  if (P == 1) {
+    const int64_t tiles = static_cast<int64_t>((m.nx + kTileX1 - 1) / kTileX1) * ((m.ny + kTileY1 - 1) / kTileY1) *
+                          ((m.nz + kTileZ1 - 1) / kTileZ1);
+    const dim3 grid(static_cast<unsigned>(tiles));
+    if (A.G) {
+      if (fused)
+        hipLaunchKernelGGL((hex_rhs_tile_kernel<1, kTileX1, kTileY1, kTileZ1, true, true>), grid, dim3(256), 0, s, A);
+      else
+        hipLaunchKernelGGL((hex_rhs_tile_kernel<1, kTileX1, kTileY1, kTileZ1, false, true>), grid, dim3(256), 0, s, A);
+    } else if (fused) {
+      hipLaunchKernelGGL((hex_rhs_tile_kernel<1, kTileX1, kTileY1, kTileZ1, true, false>), grid, dim3(256), 0, s, A);
+    } else {
+      hipLaunchKernelGGL((hex_rhs_tile_kernel<1, kTileX1, kTileY1, kTileZ1, false, false>), grid, dim3(256), 0, s, A);
+    }
+  } else if (A.G) {
     if (fused)
       hipLaunchKernelGGL((hex_rhs_kernel<P, true, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
     else
       hipLaunchKernelGGL((hex_rhs_kernel<P, false, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
-  } else if (P == 1) {
-    const int64_t tiles = static_cast<int64_t>((m.nx + kTileX1 - 1) / kTileX1) * ((m.ny + kTileY1 - 1) / kTileY1) *
-                          ((m.nz + kTileZ1 - 1) / kTileZ1);
-    if (fused)
-      hipLaunchKernelGGL((hex_rhs_tile_kernel<1, kTileX1, kTileY1, kTileZ1, true>), dim3(static_cast<unsigned>(tiles)),
-                         dim3(256), 0, s, A);
-    else
-      hipLaunchKernelGGL((hex_rhs_tile_kernel<1, kTileX1, kTileY1, kTileZ1, false>),
-                         dim3(static_cast<unsigned>(tiles)), dim3(256), 0, s, A);
   } else if (fused) {
     hipLaunchKernelGGL((hex_rhs_kernel<P, true, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
   } else {
