@@ -264,31 +264,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == 1 || (
 // tile's boundary planes or past a ragged grid end, are read from memory
 // with the periodic wrap.  Own state and output move in runs of TX cells
 // (TX Np consecutive doubles per field).
-// tile of the p = 1 kernel: 4 x 4 x 2 cells of 8 nodes
-constexpr int kTileX1 = 4, kTileY1 = 4, kTileZ1 = 2;
-
-template <int P, int TX, int TY, int TZ>
-struct HexTileCfg {
-  static constexpr int N1 = P + 1;
-  static constexpr int NP = N1 * N1 * N1;
-  static constexpr int NFP = N1 * N1;
-  static constexpr int NC = TX * TY * TZ;  // cells of the tile
-  static constexpr int NT = NC * NP;       // threads owning a node
-  static constexpr int NSX = (TX + 1) * TY * TZ * NFP;
-  static constexpr int NSY = TX * (TY + 1) * TZ * NFP;
-  static constexpr int NSZ = TX * TY * (TZ + 1) * NFP;
-  static constexpr int NS = NSX + NSY + NSZ;  // face nodes of the tile
-  static constexpr int KF = (NS + 255) / 256;
-  static_assert(NT <= 256, "one thread per node");
-};
-
-// wraps a cell coordinate into [0, n) (it lies in [-n, 2 n + T))
-__device__ inline int wrap_cell(int c, int n) {
-  c = c < 0 ? c + n : c;
-  while (c >= n) c -= n;
-  return c;
-}
-
 template <int P, int TX, int TY, int TZ, bool FUSED, bool AV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void hex_rhs_tile_kernel(HexArgs A) {
   static_assert(P == 1, "line partners by lane exchange: a cell's 8 nodes are 8 consecutive lanes");
@@ -334,63 +309,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void h
 #pragma unroll
   for (int u = 0; u < C::KF; ++u) {
     const int s = tid + 256 * u < C::NS ? tid + 256 * u : C::NS - 1;
-    int d, k, t1, t2, r;
-    if (s < C::NSX) {
-      d = 0; r = s;
-    } else if (s < C::NSX + C::NSY) {
-      d = 1; r = s - C::NSX;
-    } else {
-      d = 2; r = s - C::NSX - C::NSY;
-    }
-    const int m = r % NFP;
-    r /= NFP;
-    const int Td = d == 0 ? TX : d == 1 ? TY : TZ;
-    const int T1 = d == 0 ? TY : TX;  // first transverse extent (y for x faces, else x)
-    k = r % (Td + 1);
-    r /= Td + 1;
-    t1 = r % T1;
-    t2 = r / T1;
-    // tile-local cells of both sides: (x, y, z) with the d coordinate k - 1 (L) or k (R)
-    int cc[2][3];
+    const TileFaceNode fn = tile_face_node<P, TX, TY, TZ>(s, s == tid + 256 * u, X0, Y0, Z0, nx, ny, nz);
+    fdir[u] = fn.d;
+    fm[u] = fn.m;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int kd = k - 1 + side;
-      cc[side][0] = d == 0 ? kd : t1;
-      cc[side][1] = d == 0 ? t1 : (d == 1 ? kd : t2);
-      cc[side][2] = d == 2 ? kd : t2;
-    }
-    const int n_d = d == 0 ? nx : d == 1 ? ny : nz;
-    const int O_d = d == 0 ? X0 : d == 1 ? Y0 : Z0;
-    // transverse cells inside the grid (else no valid cell touches this face)
-    const bool trans_ok = (d == 0 ? (Y0 + t1 < ny && Z0 + t2 < nz)
-                                  : d == 1 ? (X0 + t1 < nx && Z0 + t2 < nz) : (X0 + t1 < nx && Y0 + t2 < ny));
-    const int uu = m % N1, vv = m / N1;
-    fdir[u] = d;
-    fm[u] = m;
-    bool any = false;
+      fin[u][side] = fn.in[side];
+      fcell[u][side] = fn.cell[side];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int kd = k - 1 + side;
-      const bool inside = s == tid + 256 * u && trans_ok && kd >= 0 && kd < Td && O_d + kd < n_d;
-      fin[u][side] = inside;
-      fcell[u][side] = cc[side][0] + TX * (cc[side][1] + TY * cc[side][2]);
-      any |= inside;
-      // the side's node: position P (L, its +d face) or 0 (R, its -d face) along d
-      const int pd = side ? 0 : P;
-      const int nn = d == 0 ? nidx<N1>(pd, uu, vv) : d == 1 ? nidx<N1>(uu, pd, vv) : nidx<N1>(uu, vv, pd);
-      // global cell of the side (periodic), read when it is not in the tile
-      int g3[3] = {X0 + cc[side][0], Y0 + cc[side][1], Z0 + cc[side][2]};
-      g3[d] = wrap_cell(O_d + kd, n_d);
-      const int ge = trans_ok ? g3[0] + nx * (g3[1] + ny * g3[2]) : 0;
-      const int gi = ge * NP + nn;
-#pragma unroll
-      for (int f = 0; f < 5; ++f) gq[u][side][f] = inside ? 0.0 : A.q[f * Es + gi];
+      for (int f = 0; f < 5; ++f) gq[u][side][f] = fn.in[side] ? 0.0 : A.q[f * Es + fn.gi[side]];
       if (AV) {
-        fvis[u][side] = trans_ok && A.eps[ge] > 0.0;
-        fgi[u][side] = gi;
+        fvis[u][side] = A.eps[fn.ge[side]] > 0.0;  // (element 0 where no valid cell touches the face: unused)
+        fgi[u][side] = fn.gi[side];
       }
     }
-    fuse[u] = any;
+    fuse[u] = fn.in[0] || fn.in[1];
   }
   if (own) {
 #pragma unroll

@@ -330,11 +330,157 @@ __global__ __launch_bounds__(256) void hex_limit_kernel(ShArgs A) {
   }
 }
 
+// p = 1 on the boxes of TX x TY x TZ cells of the p = 1 right-hand side: a
+// cell's 8 nodes are 8 consecutive lanes (node i = a + 2 b + 4 c), so the
+// three modal passes, the cell's reductions and the line derivatives take the
+// other node of a line from lane i ^ 1, i ^ 2 or i ^ 4 instead of LDS (the
+// reductions as a butterfly over the cell's lanes: every lane gets the same
+// bits); each face node's central jump 1/2 (q_R - q_L), the same for both
+// sides, is formed once, in-tile sides from the tile's LDS copy.
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void hex_av_flux_tile_kernel(ShArgs A) {
+  constexpr int P = 1;
+  using C = HexTileCfg<P, TX, TY, TZ>;
+  constexpr int NP = C::NP, NFP = C::NFP, NC = C::NC;
+  static_assert(C::NT == 256, "one thread per node, every thread");
+  __shared__ double s_q[NC][5][NP];
+  __shared__ double s_J[NC][6][5][NFP];
+  const int tid = threadIdx.x;
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+  const int X0 = (blockIdx.x % ntx) * TX, Y0 = ((blockIdx.x / ntx) % nty) * TY, Z0 = (blockIdx.x / (ntx * nty)) * TZ;
+  const size_t Es = static_cast<size_t>(A.E) * NP;
+  const int cl = tid / NP, ic = tid - cl * NP;
+  const int lx = cl % TX, ly = (cl / TX) % TY, lz = cl / (TX * TY);
+  const bool valid = X0 + lx < nx && Y0 + ly < ny && Z0 + lz < nz;
+  const int gx = valid ? X0 + lx : 0, gy = valid ? Y0 + ly : 0, gz = valid ? Z0 + lz : 0;
+  const int e = gx + nx * (gy + ny * gz);
+  const int idx = e * NP + ic;
+
+  // own node, and the out-of-tile sides of this thread's face nodes
+  double qv[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) qv[f] = A.q[f * Es + idx];
+  int fdir[C::KF], fm[C::KF], fcell[C::KF][2], fnn[C::KF][2];
+  bool fin[C::KF][2], fuse[C::KF];
+  double gq[C::KF][2][5];
+#pragma unroll
+  for (int u = 0; u < C::KF; ++u) {
+    const int s = tid + 256 * u < C::NS ? tid + 256 * u : C::NS - 1;
+    const TileFaceNode fn = tile_face_node<P, TX, TY, TZ>(s, s == tid + 256 * u, X0, Y0, Z0, nx, ny, nz);
+    fdir[u] = fn.d;
+    fm[u] = fn.m;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      fin[u][side] = fn.in[side];
+      fcell[u][side] = fn.cell[side];
+      fnn[u][side] = fn.gi[side] - fn.ge[side] * NP;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) gq[u][side][f] = fn.in[side] ? 0.0 : A.q[f * Es + fn.gi[side]];
+    }
+    fuse[u] = fn.in[0] || fn.in[1];
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) s_q[cl][f][ic] = qv[f];
+
+  // rho's modal coefficients: the inverse modal Vandermonde along a, b, c
+  const int a = ic & 1, bb = (ic >> 1) & 1, c = ic >> 2;
+  const double* Vi = A.sh;
+  const double va0 = a ? Vi[2] : Vi[0], va1 = a ? Vi[3] : Vi[1];
+  const double vb0 = bb ? Vi[2] : Vi[0], vb1 = bb ? Vi[3] : Vi[1];
+  const double vc0 = c ? Vi[2] : Vi[0], vc1 = c ? Vi[3] : Vi[1];
+  double t = qv[0];
+  {
+    const double o = __shfl_xor(t, 1, 64);
+    t = fma(va1, a ? t : o, fma(va0, a ? o : t, 0.0));
+  }
+  {
+    const double o = __shfl_xor(t, 2, 64);
+    t = fma(vb1, bb ? t : o, fma(vb0, bb ? o : t, 0.0));
+  }
+  {
+    const double o = __shfl_xor(t, 4, 64);
+    t = fma(vc1, c ? t : o, fma(vc0, c ? o : t, 0.0));
+  }
+  const bool top = a == P || bb == P || c == P;
+  const double ir = 1.0 / qv[0];
+  const double u = qv[1] * ir, v = qv[2] * ir, w = qv[3] * ir;
+  const double pr = (A.gamma - 1.0) * (qv[4] - 0.5 * (qv[1] * u + qv[2] * v + qv[3] * w));
+  double den = t * t, num = top ? t * t : 0.0;
+  double lam = sqrt(u * u + v * v + w * w) + sqrt(A.gamma * pr * ir);
+#pragma unroll
+  for (int k = 1; k < NP; k <<= 1) {
+    den += __shfl_xor(den, k, 64);
+    num += __shfl_xor(num, k, 64);
+    lam = fmax(lam, __shfl_xor(lam, k, 64));
+  }
+  const double h = fmin(fmin(2.0 / A.ih[gx], 2.0 / A.ih[nx + gy]), 2.0 / A.ih[nx + ny + gz]);
+  const double sv = num > 0.0 ? log10(num / den) : -INFINITY;
+  double ramp;
+  if (sv < A.s0 - A.kappa) ramp = 0.0;
+  else if (sv > A.s0 + A.kappa) ramp = 1.0;
+  else ramp = 0.5 * (1.0 + sin(3.14159265358979323846 * (sv - A.s0) / (2.0 * A.kappa)));
+  const double eps = A.c_eps * h / P * lam * ramp;
+  if (valid && ic == 0) {
+    if (A.s_out) A.s_out[e] = sv;
+    if (A.eps_out) A.eps_out[e] = eps;
+  }
+
+  // lifted gradients and the viscous flux only in tiles holding a viscous
+  // element (the block barrier also completes the LDS copy of the state)
+  if (!__syncthreads_or(valid && eps > 0.0)) return;
+#pragma unroll
+  for (int u = 0; u < C::KF; ++u) {
+    if (!fuse[u]) continue;
+    const int d = fdir[u], m = fm[u];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const double qL = fin[u][0] ? s_q[fcell[u][0]][f][fnn[u][0]] : gq[u][0][f];
+      const double qR = fin[u][1] ? s_q[fcell[u][1]][f][fnn[u][1]] : gq[u][1][f];
+      const double j = 0.5 * (qR - qL);  // n_d (q+ - q-) / 2 on both sides
+      if (fin[u][0]) s_J[fcell[u][0]][2 * d + 1][f][m] = j;
+      if (fin[u][1]) s_J[fcell[u][1]][2 * d][f][m] = j;
+    }
+  }
+  __syncthreads();
+  if (!(valid && eps > 0.0)) return;
+  const double* D1 = A.op;
+  const double* lift = A.op + 4;
+  const double da0 = a ? D1[2] : D1[0], da1 = a ? D1[3] : D1[1];
+  const double db0 = bb ? D1[2] : D1[0], db1 = bb ? D1[3] : D1[1];
+  const double dc0 = c ? D1[2] : D1[0], dc1 = c ? D1[3] : D1[1];
+  const double la0 = a ? lift[2] : lift[0], la1 = a ? lift[3] : lift[1];
+  const double lb0 = bb ? lift[2] : lift[0], lb1 = bb ? lift[3] : lift[1];
+  const double lc0 = c ? lift[2] : lift[0], lc1 = c ? lift[3] : lift[1];
+  const double ihx = A.ih[gx], ihy = A.ih[nx + gy], ihz = A.ih[nx + ny + gz];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const double qf = qv[f];
+    const double px = __shfl_xor(qf, 1, 64), py = __shfl_xor(qf, 2, 64), pz = __shfl_xor(qf, 4, 64);
+    double gxv = fma(da1, a ? qf : px, fma(da0, a ? px : qf, 0.0));
+    double gyv = fma(db1, bb ? qf : py, fma(db0, bb ? py : qf, 0.0));
+    double gzv = fma(dc1, c ? qf : pz, fma(dc0, c ? pz : qf, 0.0));
+    gxv += la0 * s_J[cl][0][f][bb + 2 * c] + la1 * s_J[cl][1][f][bb + 2 * c];
+    gyv += lb0 * s_J[cl][2][f][a + 2 * c] + lb1 * s_J[cl][3][f][a + 2 * c];
+    gzv += lc0 * s_J[cl][4][f][a + 2 * bb] + lc1 * s_J[cl][5][f][a + 2 * bb];
+    A.G[(0 * 5 + f) * Es + idx] = eps * (ihx * gxv);
+    A.G[(1 * 5 + f) * Es + idx] = eps * (ihy * gyv);
+    A.G[(2 * 5 + f) * Es + idx] = eps * (ihz * gzv);
+  }
+}
+
 template <int P>
 dg_status launch_av_p(const HexMesh& m, const ShArgs& A, hipStream_t s) {
   using C = ShCfg<P>;
   const int64_t blocks = (m.E + C::EPB - 1) / C::EPB;
-  hipLaunchKernelGGL((hex_av_flux_kernel<P>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+  if (P == 1) {
+    const int64_t tiles = static_cast<int64_t>((m.nx + kTileX1 - 1) / kTileX1) * ((m.ny + kTileY1 - 1) / kTileY1) *
+                          ((m.nz + kTileZ1 - 1) / kTileZ1);
+    hipLaunchKernelGGL((hex_av_flux_tile_kernel<kTileX1, kTileY1, kTileZ1>), dim3(static_cast<unsigned>(tiles)),
+                       dim3(256), 0, s, A);
+  } else {
+    hipLaunchKernelGGL((hex_av_flux_kernel<P>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A);
+  }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? DG_OK : hip_fail(e, "hex viscosity launch");
 }
