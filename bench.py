@@ -616,7 +616,7 @@ def hex_leg(dg, hexdg, wl, dev, stream, steps, warmup):
                      "value": round(m.E * m.Np * NF / (ms * 1e-3) / 1e9, 3), "unit": "GDOF·fields/s",
                      "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                   "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_elem": bytes_el,
-                                  "kernel": f"hex_rhs_kernel<{p}>"},
+                                  "kernel": "hex_rhs_tile_kernel<1, 4, 4, 2>" if p == 1 else f"hex_rhs_kernel<{p}>"},
                      "lsrk_step_ms": round(ms_rk, 4), "overintegrated": oi_rec}
         del q, r, work, qs
         m.close()
@@ -684,7 +684,8 @@ def shock_leg(dg, hexdg, wl, dev, stream, steps, warmup):
                      "unit": "GDOF·fields/s (RHS with artificial viscosity)",
                      "roofline": {"bound": "hbm", "achieved": round(gbs_av, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                   "frac": round(gbs_av / PEAK_HBM_GBS, 4), "bytes": int(bytes_av),
-                                  "kernels": "hex_av_flux_kernel + hex_rhs_kernel (viscous variant)"},
+                                  "kernels": ("hex_av_flux_tile_kernel + hex_rhs_tile_kernel (viscous variant)" if p == 1
+                                              else "hex_av_flux_kernel + hex_rhs_kernel (viscous variant)")},
                      "state_finite": bool(torch.isfinite(qs).all()), "min_density_after_steps": float(qs[0].min())}
         del q, r, G, eps, work, wplain, ql, qs, qp
         m.close()
