@@ -50,6 +50,33 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2512_17101_amd", "csrc", f) for f in ("
 ALGORITHMIC = {1: (2640, 552), 2: (9000, 1032), 3: (26400, 1832), 4: (67950, 3032)}
 
 
+# The paper's own right-hand-side throughputs (Sec. 5.3, the shock wave /
+# boundary layer interaction case: 2-D, degree-1 tensor-product elements,
+# full compressible Navier-Stokes; "DOFs" counted per scalar field).  Quoted
+# as context with the hardware the paper names: none of them is this
+# workload, and the paper states no precision for them.
+PAPER_FIGURES = [
+    {"system": "MIRGE-Com", "value": 1.6e6, "unit": "DOFs/s (per field)", "hardware": "Apple M2 (CPU)"},
+    {"system": "Ryujin (comparison code)", "value": 3.8e6, "unit": "DOFs/s (per field)", "hardware": "Apple M2 (CPU)"},
+    {"system": "MIRGE-Com", "value": 100.4e6, "unit": "DOFs/s (per field)", "hardware": "AMD MI300A"},
+]
+
+
+def paper_context(rec):
+    """The paper's figures beside the closest leg measured here (the p = 1
+    hexahedron shock slab: RHS with artificial viscosity, 3-D Euler), in the
+    paper's unit (nodes x RHS evaluations per second, per field)."""
+    out = {"source": "Sec. 5.3 (shock wave / boundary layer interaction, 2-D, degree-1 TPEs, Navier-Stokes)",
+           "figures": PAPER_FIGURES}
+    sh = rec.get("shock", {}).get("hex_shock_slab_p1_120cubed")
+    if sh:
+        nodes = sh["elements"] * 8
+        out["closest_here"] = {"leg": "hex_shock_slab_p1_120cubed (RHS with artificial viscosity, 3-D Euler)",
+                               "value": round(nodes / (sh["ms_rhs_with_av"] * 1e-3), 1),
+                               "unit": "DOFs/s (per field)", "hardware": "AMD MI355X (one GPU)"}
+    return out
+
+
 def algorithmic_counts(p: int):
     """(flops, bytes) per element of one Euler RHS (the table above)."""
     return ALGORITHMIC[p]
@@ -860,6 +887,7 @@ def main():
         torch.cuda.empty_cache()
         rec["reacting"] = reacting_leg(dg, wl, dev, stream, max(2, args.steps // 5))
         rec["learned_guess"] = learned_leg(dg, wl, dev, stream, X)
+    rec["paper_context"] = paper_context(rec)
     print(json.dumps(rec), flush=True)
 
 

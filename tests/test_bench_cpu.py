@@ -77,3 +77,15 @@ def test_stored_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
         assert bench.stored_traffic() is None
         c.write_bytes(original)
         assert bench.stored_traffic() == 1234.0
+
+
+def test_paper_context_quotes_the_papers_figures():
+    """The bench line quotes the paper's RHS throughputs (Sec. 5.3) with
+    their hardware, and the closest leg measured here in the same unit."""
+    import bench
+    ctx = bench.paper_context({"shock": {"hex_shock_slab_p1_120cubed": {"elements": 1000, "ms_rhs_with_av": 2.0}}})
+    hw = {(f["system"], f["hardware"]): f["value"] for f in ctx["figures"]}
+    assert hw[("MIRGE-Com", "AMD MI300A")] == 100.4e6
+    assert hw[("MIRGE-Com", "Apple M2 (CPU)")] == 1.6e6
+    assert ctx["closest_here"]["value"] == 8000 / 2e-3
+    assert "closest_here" not in bench.paper_context({})
