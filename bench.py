@@ -102,11 +102,13 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def stored_counters():
+def stored_counters(launch=None):
     """Figures per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source: HBM traffic in bytes
+    was taken on the current kernel source and, given `launch` (a launch
+    configuration dict), in the same launch shape (tiles per block, LDS
+    staging, XCD run length): HBM traffic in bytes
     (traffic_bytes_per_launch) and the matrix-core busy fraction
-    (mfma_busy_frac).  Empty if the sources changed since."""
+    (mfma_busy_frac).  Empty otherwise."""
     if not os.path.exists(PMC_SUMMARY):
         return {}
     kv = {}
@@ -116,6 +118,10 @@ def stored_counters():
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != kernel_source_sha():
         return {}
+    if launch is not None:
+        for k in ("waves_per_block", "lds_stage", "xcd_run"):
+            if kv.get("launch_" + k) != str(launch[k]):
+                return {}
     out = {}
     if "traffic_bytes_per_launch" in kv:
         out["traffic"] = float(kv["traffic_bytes_per_launch"])
@@ -266,18 +272,21 @@ def time_rhs(dg, mesh, q, out, precision, steps, warmup, stream):
 
 
 def time_rk_step(dg, mesh, q, work, dt, precision, steps, stream):
+    """Average duration of one dg_rk_step (five stages), HIP events on its
+    stream: SETTLE_S / 2 seconds of untimed steps, then 1 + REPEATS batches of
+    `steps` steps; the first batch is the reported figure, all of them the
+    spread."""
     import torch
+    launch = lambda: dg.rk_step(mesh, q, work, 0.0, dt, precision, stream=stream)
     with torch.cuda.stream(stream):
-        dg.rk_step(mesh, q, work, 0.0, dt, precision, stream=stream)
-        stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            dg.rk_step(mesh, q, work, 0.0, dt, precision, stream=stream)
-        e1.record(stream)
-        stream.synchronize()
-    return e0.elapsed_time(e1) / steps
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < SETTLE_S / 2:
+            for _ in range(10):
+                launch()
+            stream.synchronize()
+        batches = [_time_ms(stream, launch, steps) for _ in range(1 + REPEATS)]
+    return batches[0], {"median": round(float(np.median(batches)), 4), "min": round(min(batches), 4),
+                        "max": round(max(batches), 4), "batches": len(batches), "steps_per_batch": steps}
 
 
 def batched_leg(dg, wl, dev, stream, steps):
@@ -821,8 +830,13 @@ def main():
     torch.cuda.synchronize()
     E, Np = mesh.E, mesh.Np
     modes = ["fp64", "fp32", "split_bf16"] if args.precision == "all" else [args.precision]
-    outs, ms, spread = {}, {}, {}
+    outs, ms, spread, tuned = {}, {}, {}, {}
     for mode in modes:
+        # the launch shape (tiles per block, fused or split stages, LDS
+        # staging, XCD run length) from the autotuner, which times whole
+        # Runge-Kutta steps of this mesh; the RHS and the step timings use it
+        with torch.cuda.stream(stream):
+            tuned[mode], _ = mesh.autotune(mode, trials=3, stream=stream)
         outs[mode] = torch.empty_like(q)
         ms[mode], spread[mode] = time_rhs(dg, mesh, q, outs[mode], mode, args.steps, args.warmup, stream)
     torch.cuda.synchronize()
@@ -834,7 +848,7 @@ def main():
     achieved_gbs = bytes_ * E / (ms[head] * 1e-3) / 1e9
     # the stored counters describe the FP64 kernel on the 48^3 workload only
     on_workload = args.n == WORKLOAD["n"]
-    counters = stored_counters() if head == "fp64" and on_workload else {}
+    counters = stored_counters(tuned[head]) if head == "fp64" and on_workload else {}
     copy_bw = copy_bandwidth(dev, stream)  # measured after the timed launches
     hbm_view = {"achieved": round(achieved_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved_gbs / PEAK_HBM_GBS, 4), "measured_copy_gbs": copy_bw["gbs"],
@@ -857,12 +871,14 @@ def main():
            "config": {"workload": WORKLOAD["name"] if on_workload else f"euler_vortex_pert_p3_{args.n}cubed",
                       "elements": E, "order": p, "nodes_per_element": Np, "fields": NF,
                       "contraction_precision": head},
-           "roofline": roofline, "ms_per_step_spread": spread[head], "copy_bandwidth": copy_bw}
+           "roofline": roofline, "ms_per_step_spread": spread[head], "copy_bandwidth": copy_bw,
+           "launch": tuned[head]}
     variants = {}
     for mode in modes[1:]:
         gbs = bytes_ * E / (ms[mode] * 1e-3) / 1e9
         variants[mode] = {"value": round(E * Np * NF / (ms[mode] * 1e-3) / 1e9, 3), "ms_per_step": round(ms[mode], 5),
                           "ms_per_step_spread": spread[mode], "speedup_vs_fp64": round(ms[head] / ms[mode], 3),
+                          "launch": tuned[mode],
                           "hbm_view": {"achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                        "frac": round(gbs / PEAK_HBM_GBS, 4), "measured_copy_gbs": copy_bw["gbs"],
                                        "frac_of_measured_copy": round(gbs / copy_bw["gbs"], 4)}}
@@ -870,12 +886,9 @@ def main():
         work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
         qs = q.clone()
         for mode in modes:
-            # the step's launch shape (tiles per block, fused or split stages) from the autotuner
-            with torch.cuda.stream(stream):
-                cfg, _ = mesh.autotune(mode, trials=2, stream=stream)
-            t_rk = time_rk_step(dg, mesh, qs, work, 1e-4, mode, max(2, args.steps // 10), stream)
+            t_rk, sp_rk = time_rk_step(dg, mesh, qs, work, 1e-4, mode, max(2, args.steps // 10), stream)
             (rec if mode == head else variants[mode])["lsrk_step_ms"] = round(t_rk, 4)
-            (rec if mode == head else variants[mode])["lsrk_launch"] = cfg
+            (rec if mode == head else variants[mode])["lsrk_step_ms_spread"] = sp_rk
         if len(modes) > 1 and args.long_steps > 0:
             rec["after_steps"] = long_run_errors(dg, mesh, q, q_np, work, modes, args.long_steps, stream)
         del work, qs

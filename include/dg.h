@@ -183,8 +183,15 @@ typedef struct {
                           global-to-LDS loads where that path exists (FP64
                           and FP32 contractions, Np a multiple of 4, q
                           16-byte aligned), 0 = through registers */
+  int xcd_run;         /* FP64 kernel (the FP32 / BF16 kernels accept and
+                          ignore it): workgroups are dispatched round-robin
+                          to the 8 XCDs (each with its own L2); with
+                          xcd_run = k > 1 each XCD takes runs of k
+                          consecutive blocks of tiles, all XCDs still
+                          sweeping the mesh together, so that neighbouring
+                          tiles share an L2.  1 .. 64; 1 = plain order */
 } dg_launch_config;
-/* Initial configuration of every precision: {4, 1, 1}.  Set and get are
+/* Initial configuration of every precision: {4, 1, 1, 1}.  Set and get are
  * synchronous host calls that must not overlap calls running on the mesh. */
 dg_status dg_mesh_set_launch(dg_mesh m, dg_precision prec, const dg_launch_config* cfg);
 dg_status dg_mesh_get_launch(dg_mesh m, dg_precision prec, dg_launch_config* cfg);

@@ -107,7 +107,7 @@ struct Mesh {
   int* d_fmask = nullptr;         // [4][Nfp]
   uint8_t* d_nbtab = nullptr;     // [4][24][Nfp]
   // launch configuration per contraction precision (dg_precision index)
-  dg_launch_config launch[3] = {{4, 1, 1}, {4, 1, 1}, {4, 1, 1}};
+  dg_launch_config launch[3] = {{4, 1, 1, 1}, {4, 1, 1, 1}, {4, 1, 1, 1}};
 };
 
 // Buffers of stage s of a fused five-stage LSRK step over the caller's state

@@ -55,6 +55,7 @@ struct RhsArgs {
   int64_t E, Epad;
   int ntiles;
   int dma;  // q is 16-byte aligned and the launch configuration asks for the LDS DMA staging
+  int xcd_run;  // blocks per XCD run (1: plain order)
   double gamma, a, b, dt;
   unsigned* flags;  // device failure flags (non-finite output)
 };
@@ -90,7 +91,19 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ?
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
-  const int tile = blockIdx.x * TL::WAVES + wave;
+  // Workgroups go round-robin to the 8 XCDs.  With xcd_run = k > 1, XCD x
+  // takes the blocks x k .. x k + k - 1 of each run of 8 k blocks, so that
+  // neighbouring tiles share its L2 while all XCDs sweep the mesh together
+  // (the tail past the last whole run keeps the plain order: a bijection).
+  int blk = blockIdx.x;
+  {
+    const int k = A.xcd_run, full = static_cast<int>(gridDim.x) / (8 * k) * (8 * k);
+    if (k > 1 && blk < full) {
+      const int i = blk >> 3;
+      blk = ((i / k) * 8 + (blk & 7)) * k + i % k;
+    }
+  }
+  const int tile = blk * TL::WAVES + wave;
   if (tile >= A.ntiles) return;  // uniform per wave; no block barrier follows
   const int n = lane & 15, g = lane >> 4;
   const int64_t e0 = static_cast<int64_t>(tile) * 16;
@@ -282,6 +295,7 @@ dg_status launch_rhs_euler_fp64(const Mesh& m, double gamma, const double* q, do
   A.Epad = m.Epad;
   A.ntiles = static_cast<int>(m.Epad / 16);
   A.dma = (reinterpret_cast<uintptr_t>(q) & 15u) == 0 && m.launch[DG_FP64].lds_stage ? 1 : 0;
+  A.xcd_run = m.launch[DG_FP64].xcd_run;
   A.gamma = gamma;
   A.a = a;
   A.b = b;

@@ -16,7 +16,7 @@ bool valid_prec(dg_precision p) { return p == DG_FP64 || p == DG_FP32 || p == DG
 
 bool valid_launch(const dg_launch_config& c) {
   return (c.waves_per_block == 2 || c.waves_per_block == 4) && (c.rk_fused == 0 || c.rk_fused == 1) &&
-         (c.lds_stage == 0 || c.lds_stage == 1);
+         (c.lds_stage == 0 || c.lds_stage == 1) && c.xcd_run >= 1 && c.xcd_run <= 64;
 }
 
 const char* prec_name(dg_precision p) { return p == DG_FP64 ? "fp64" : p == DG_FP32 ? "fp32" : "split_bf16"; }
@@ -27,7 +27,8 @@ extern "C" dg_status dg_mesh_set_launch(dg_mesh h, dg_precision prec, const dg_l
   if (!h || !cfg) return fail(DG_ERR_ARG, "dg_mesh_set_launch: null argument");
   if (!valid_prec(prec)) return fail(DG_ERR_ARG, "dg_mesh_set_launch: unknown precision");
   if (!valid_launch(*cfg))
-    return fail(DG_ERR_ARG, "dg_mesh_set_launch: waves_per_block must be 2 or 4, rk_fused and lds_stage 0 or 1");
+    return fail(DG_ERR_ARG,
+                "dg_mesh_set_launch: waves_per_block must be 2 or 4, rk_fused and lds_stage 0 or 1, xcd_run 1..64");
   reinterpret_cast<Mesh*>(h)->launch[prec] = *cfg;
   return DG_OK;
 }
@@ -56,10 +57,10 @@ extern "C" dg_status dg_autotune(dg_mesh h, const dg_params* prm, dg_precision p
   if (cache_path) {
     cache = read_cache(cache_path);
     const auto it = cache.find(key);
-    double w, f, l;
+    double w, f, l, x;
     if (it != cache.end() && cache_field(it->second, "waves_per_block", w) && cache_field(it->second, "rk_fused", f) &&
-        cache_field(it->second, "lds_stage", l)) {
-      const dg_launch_config c{static_cast<int>(w), static_cast<int>(f), static_cast<int>(l)};
+        cache_field(it->second, "lds_stage", l) && cache_field(it->second, "xcd_run", x)) {
+      const dg_launch_config c{static_cast<int>(w), static_cast<int>(f), static_cast<int>(l), static_cast<int>(x)};
       if (valid_launch(c)) {
         m.launch[prec] = c;
         if (chosen) *chosen = c;
@@ -95,7 +96,9 @@ extern "C" dg_status dg_autotune(dg_mesh h, const dg_params* prm, dg_precision p
   } ev{e0, e1};
 
   // tiles per block x fused stages x LDS staging path (only where the
-  // direct global-to-LDS staging exists: FP64 / FP32 with Np % 4 == 0)
+  // direct global-to-LDS staging exists: FP64 / FP32 with Np % 4 == 0) x
+  // XCD run length (FP64 only; 9 and 27 blocks were the good runs measured
+  // on box meshes, 1 is the plain order)
   const bool has_dma = m.Np % 4 == 0 && prec != DG_SPLIT_BF16;
   std::vector<dg_launch_config> cands;
   for (int w : {4, 2}) {
@@ -103,7 +106,10 @@ extern "C" dg_status dg_autotune(dg_mesh h, const dg_params* prm, dg_precision p
     for (int f : {1, 0})
       for (int l : {1, 0}) {
         if (l == 0 && !has_dma) continue;  // the same kernel as l = 1
-        cands.push_back(dg_launch_config{w, f, l});
+        for (int x : {1, 9, 27}) {
+          if (x > 1 && prec != DG_FP64) continue;  // the other kernels keep the plain order
+          cands.push_back(dg_launch_config{w, f, l, x});
+        }
       }
   }
   const dg_launch_config prev = m.launch[prec];
@@ -142,9 +148,10 @@ extern "C" dg_status dg_autotune(dg_mesh h, const dg_params* prm, dg_precision p
   if (chosen) *chosen = best;
   if (best_ms) *best_ms = best_t;
   if (cache_path) {
-    char obj[192];
-    std::snprintf(obj, sizeof obj, "{\"waves_per_block\": %d, \"rk_fused\": %d, \"lds_stage\": %d, \"ms\": %.6g}",
-                  best.waves_per_block, best.rk_fused, best.lds_stage, best_t);
+    char obj[224];
+    std::snprintf(obj, sizeof obj,
+                  "{\"waves_per_block\": %d, \"rk_fused\": %d, \"lds_stage\": %d, \"xcd_run\": %d, \"ms\": %.6g}",
+                  best.waves_per_block, best.rk_fused, best.lds_stage, best.xcd_run, best_t);
     cache[key] = obj;
     if (!write_cache(cache_path, cache))
       return fail(DG_ERR_ARG, std::string("dg_autotune: cannot write cache file ") + cache_path);

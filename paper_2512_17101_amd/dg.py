@@ -40,7 +40,8 @@ class DGError(RuntimeError):
 
 class LaunchConfig(ctypes.Structure):
     """dg_launch_config: one mesh's RHS / Runge-Kutta launch shape for one precision."""
-    _fields_ = [("waves_per_block", ctypes.c_int), ("rk_fused", ctypes.c_int), ("lds_stage", ctypes.c_int)]
+    _fields_ = [("waves_per_block", ctypes.c_int), ("rk_fused", ctypes.c_int), ("lds_stage", ctypes.c_int),
+                ("xcd_run", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -194,8 +195,9 @@ class Mesh:
         _check(lib().dg_mesh_nodes(self._h, _np_ptr(out)))
         return out
 
-    def set_launch(self, mode: str = "fp64", waves_per_block: int = 4, rk_fused: int = 1, lds_stage: int = 1):
-        c = LaunchConfig(waves_per_block, rk_fused, lds_stage)
+    def set_launch(self, mode: str = "fp64", waves_per_block: int = 4, rk_fused: int = 1, lds_stage: int = 1,
+                   xcd_run: int = 1):
+        c = LaunchConfig(waves_per_block, rk_fused, lds_stage, xcd_run)
         _check(lib().dg_mesh_set_launch(self._h, PRECISIONS[mode], ctypes.byref(c)))
 
     def get_launch(self, mode: str = "fp64") -> dict:

@@ -79,6 +79,26 @@ def test_stored_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
         assert bench.stored_traffic() == 1234.0
 
 
+def test_stored_counters_follow_the_launch_shape(tmp_path, monkeypatch):
+    """Counters taken in one launch shape are not reported for another: the
+    XCD run length changes the L2 reuse and with it the traffic."""
+    summary = tmp_path / "pmc.txt"
+    summary.write_text(f"kernel_source_sha256: {bench.kernel_source_sha()}\nlaunch_waves_per_block: 4\n"
+                       "launch_lds_stage: 1\nlaunch_xcd_run: 27\ntraffic_bytes_per_launch: 99.0\n"
+                       "mfma_busy_frac: 0.5\n")
+    monkeypatch.setattr(bench, "PMC_SUMMARY", str(summary))
+    same = dict(waves_per_block=4, rk_fused=0, lds_stage=1, xcd_run=27)
+    assert bench.stored_counters(same) == {"traffic": 99.0, "mfma_busy": 0.5}
+    for k, v in (("waves_per_block", 2), ("lds_stage", 0), ("xcd_run", 9)):
+        assert bench.stored_counters(dict(same, **{k: v})) == {}, k
+
+
+def test_committed_counter_summary_matches_the_sources():
+    """The committed FP64 counter summary was taken on the current kernel
+    sources (else the bench line would report no traffic)."""
+    assert bench.stored_counters().get("traffic", 0) > 0
+
+
 def test_paper_context_quotes_the_papers_figures():
     """The bench line quotes the paper's RHS throughputs (Sec. 5.3) with
     their hardware, and the closest leg measured here in the same unit."""
