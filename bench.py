@@ -246,6 +246,19 @@ def field_errors(got, ref):
     return {nm: {"l2": float(l2[f] / n2[f]), "linf": float(li[f] / ni[f])} for f, nm in enumerate(FIELDS)}
 
 
+# Launch shape of the single-mesh legs: four tiles per block, fused stages,
+# LDS DMA staging, XCD runs of 27 blocks (the autotuner's usual choice on
+# the 48^3 workload; fixed so that every run times the same kernels)
+DEFAULT_LAUNCH = "4,1,1,27"
+
+
+def parse_launch(text):
+    vals = [int(v) for v in text.split(",")]
+    if len(vals) != 4:
+        raise ValueError(f"--launch wants four integers or 'auto', got {text!r}")
+    return vals
+
+
 SETTLE_S = 0.5  # seconds of untimed launches before the first timed batch (clocks ramp up)
 REPEATS = 5    # batches of `steps` launches timed after the reported one, for the spread
 
@@ -770,6 +783,9 @@ def main():
     ap.add_argument("--long-steps", type=int, default=100,
                     help="LSRK steps of the reduced-precision forms against the FP64 form (0: skip)")
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="cubes per side (default: the 48^3 workload)")
+    ap.add_argument("--launch", default=DEFAULT_LAUNCH,
+                    help="launch shape of the single-mesh legs, 'waves_per_block,rk_fused,lds_stage,xcd_run' "
+                         "for every precision, or 'auto' for the autotuner's choice per precision")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched leg")
     ap.add_argument("--no-hex", action="store_true", help="skip the hexahedron leg")
     ap.add_argument("--no-shock", action="store_true", help="skip the shock-capturing leg")
@@ -833,10 +849,16 @@ def main():
     outs, ms, spread, tuned = {}, {}, {}, {}
     for mode in modes:
         # the launch shape (tiles per block, fused or split stages, LDS
-        # staging, XCD run length) from the autotuner, which times whole
-        # Runge-Kutta steps of this mesh; the RHS and the step timings use it
-        with torch.cuda.stream(stream):
-            tuned[mode], _ = mesh.autotune(mode, trials=3, stream=stream)
+        # staging, XCD run length): fixed, so that runs and profiles of the
+        # bench time the same kernels, or the autotuner's choice (it times
+        # whole Runge-Kutta steps of this mesh, and candidates within its
+        # noise may win)
+        if args.launch == "auto":
+            with torch.cuda.stream(stream):
+                mesh.autotune(mode, trials=3, stream=stream)
+        else:
+            mesh.set_launch(mode, *parse_launch(args.launch))
+        tuned[mode] = mesh.get_launch(mode)
         outs[mode] = torch.empty_like(q)
         ms[mode], spread[mode] = time_rhs(dg, mesh, q, outs[mode], mode, args.steps, args.warmup, stream)
     torch.cuda.synchronize()

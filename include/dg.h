@@ -183,8 +183,8 @@ typedef struct {
                           global-to-LDS loads where that path exists (FP64
                           and FP32 contractions, Np a multiple of 4, q
                           16-byte aligned), 0 = through registers */
-  int xcd_run;         /* FP64 kernel (the FP32 / BF16 kernels accept and
-                          ignore it): workgroups are dispatched round-robin
+  int xcd_run;         /* single-mesh RHS and stage kernels (the batch
+                          ignores it): workgroups are dispatched round-robin
                           to the 8 XCDs (each with its own L2); with
                           xcd_run = k > 1 each XCD takes runs of k
                           consecutive blocks of tiles, all XCDs still

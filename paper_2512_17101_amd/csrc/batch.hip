@@ -74,6 +74,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2))) v
     A.E = M.E;
     A.Epad = M.Epad;
     A.ntiles = static_cast<int>(M.Epad / 16);
+    A.xcd_run = 1;
     A.gamma = L.gamma;
     A.a = a;
     A.b = b;
@@ -133,6 +134,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P < 4 ? 3 :
   A.E = M.E;
   A.Epad = M.Epad;
   A.ntiles = static_cast<int>(M.Epad / 16);
+  A.xcd_run = 1;
   A.gamma = L.gamma;
   A.a = a;
   A.b = b;

@@ -85,6 +85,19 @@ __device__ inline void lf_jump(const double qm[5], const double qp[5], double Nx
   D[4] = 0.5 * ((qm[4] + pm) * Unm - (qp[4] + pp) * Unp) - 0.5 * lamFs * (qm[4] - qp[4]);
 }
 
+// Block renumbering for the 8 XCDs, which take workgroups round-robin and
+// each have their own L2: with k > 1, XCD x runs the blocks x k .. x k + k - 1
+// of each run of 8 k blocks, so that neighbouring tiles (which read each
+// other's traces) share an L2 while all XCDs still sweep the mesh together.
+// Blocks past the last whole run keep the plain order; a bijection of
+// [0, nblocks) for every k >= 1.
+__device__ inline int xcd_run_block(int blk, int nblocks, int k) {
+  const int full = nblocks / (8 * k) * (8 * k);
+  if (k <= 1 || blk >= full) return blk;
+  const int i = blk >> 3;
+  return ((i / k) * 8 + (blk & 7)) * k + i % k;
+}
+
 // Copies the face tables of order P's element (neighbour volume node of each
 // face node per face and neighbour code, nbtab [4][24][Nfp] bytes; face-node
 // mask fmask [4 Nfp]) into LDS, thread t of NT: every load is issued before

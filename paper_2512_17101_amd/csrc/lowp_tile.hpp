@@ -82,6 +82,7 @@ struct LowArgs {
   const uint8_t* __restrict__ nbtab;
   int64_t E, Epad;
   int ntiles;
+  int xcd_run;  // single-mesh kernel: blocks per XCD run (1: plain order)
   double gamma, a, b, dt;
   unsigned* flags;  // device failure flags (non-finite output); may be null
 };

@@ -91,19 +91,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ?
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
-  // Workgroups go round-robin to the 8 XCDs.  With xcd_run = k > 1, XCD x
-  // takes the blocks x k .. x k + k - 1 of each run of 8 k blocks, so that
-  // neighbouring tiles share its L2 while all XCDs sweep the mesh together
-  // (the tail past the last whole run keeps the plain order: a bijection).
-  int blk = blockIdx.x;
-  {
-    const int k = A.xcd_run, full = static_cast<int>(gridDim.x) / (8 * k) * (8 * k);
-    if (k > 1 && blk < full) {
-      const int i = blk >> 3;
-      blk = ((i / k) * 8 + (blk & 7)) * k + i % k;
-    }
-  }
-  const int tile = blk * TL::WAVES + wave;
+  const int tile = xcd_run_block(blockIdx.x, gridDim.x, A.xcd_run) * TL::WAVES + wave;
   if (tile >= A.ntiles) return;  // uniform per wave; no block barrier follows
   const int n = lane & 15, g = lane >> 4;
   const int64_t e0 = static_cast<int64_t>(tile) * 16;

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lowp_wpe
   // the operator table is read from memory (cache-resident): LDS holds the states
   const uint32_t* op = MODE == 1 ? reinterpret_cast<const uint32_t*>(A.op32) : reinterpret_cast<const uint32_t*>(A.opbf);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in scalar registers
-  const int64_t tile = static_cast<int64_t>(blockIdx.x) * W + wave;
+  const int64_t tile = static_cast<int64_t>(xcd_run_block(blockIdx.x, gridDim.x, A.xcd_run)) * W + wave;
   if (tile < A.ntiles) lowp_tile<P, MODE, FUSED, true, DMA>(A, op, s_nb, s_fm, tile, s_q[wave]);
 }
 
@@ -119,6 +119,7 @@ dg_status launch_rhs_euler_lowp(const Mesh& m, dg_precision prec, double gamma, 
   A.E = m.E;
   A.Epad = m.Epad;
   A.ntiles = static_cast<int>(m.Epad / 16);
+  A.xcd_run = m.launch[prec == DG_SPLIT_BF16 ? DG_SPLIT_BF16 : DG_FP32].xcd_run;
   A.gamma = gamma;
   A.a = a;
   A.b = b;

@@ -97,8 +97,8 @@ extern "C" dg_status dg_autotune(dg_mesh h, const dg_params* prm, dg_precision p
 
   // tiles per block x fused stages x LDS staging path (only where the
   // direct global-to-LDS staging exists: FP64 / FP32 with Np % 4 == 0) x
-  // XCD run length (FP64 only; 9 and 27 blocks were the good runs measured
-  // on box meshes, 1 is the plain order)
+  // XCD run length (9 and 27 blocks were the good runs measured on box
+  // meshes, 1 is the plain order)
   const bool has_dma = m.Np % 4 == 0 && prec != DG_SPLIT_BF16;
   std::vector<dg_launch_config> cands;
   for (int w : {4, 2}) {
@@ -106,10 +106,7 @@ extern "C" dg_status dg_autotune(dg_mesh h, const dg_params* prm, dg_precision p
     for (int f : {1, 0})
       for (int l : {1, 0}) {
         if (l == 0 && !has_dma) continue;  // the same kernel as l = 1
-        for (int x : {1, 9, 27}) {
-          if (x > 1 && prec != DG_FP64) continue;  // the other kernels keep the plain order
-          cands.push_back(dg_launch_config{w, f, l, x});
-        }
+        for (int x : {1, 9, 27}) cands.push_back(dg_launch_config{w, f, l, x});
       }
   }
   const dg_launch_config prev = m.launch[prec];

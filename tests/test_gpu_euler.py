@@ -295,30 +295,33 @@ def test_launch_configurations_give_the_same_bits(p):
 
 @pytest.mark.parametrize("p", [1, 3, 4])
 def test_xcd_runs_permute_tiles_only(p):
-    """A run length of k blocks per XCD only renumbers the FP64 tiles: on a
-    mesh with whole runs and a ragged tail (k = 2 and 5, both block widths),
-    the right-hand side and the fused steps are bitwise those of the plain
-    order, and every entry is written (outputs start as NaN)."""
+    """A run length of k blocks per XCD only renumbers the tiles: on a mesh
+    with whole runs and a ragged tail (k = 2 and 5, both block widths, every
+    contraction precision), the right-hand side and the fused steps are
+    bitwise those of the plain order, and every entry is written (outputs
+    start as NaN)."""
     dev = _dev()
     c = _case(p, (8, 8, 8), pert_seed=2011)
     mesh = dg.Mesh(p, c["xyz"], c["vid"])
     q0 = torch.from_numpy(np.ascontiguousarray(c["q"])).to(dev)
     dt = 0.2 * oe.cfl_dt(c["ops"], c["geo"], c["q"], 1.0)
-    ref = None
-    for w, x in itertools.product((4, 2), (1, 2, 5)):
-        mesh.set_launch("fp64", w, 1, 1, x)
-        out = torch.full_like(q0, float("nan"))
-        dg.rhs(mesh, q0, out, "fp64")
-        q = q0.clone()
-        work = torch.full((2,) + tuple(q.shape), float("nan"), dtype=torch.float64, device=dev)
-        for s in range(2):
-            dg.rk_step(mesh, q, work, s * dt, dt, "fp64")
-        torch.cuda.synchronize()
-        assert not torch.isnan(out).any() and not torch.isnan(q).any(), f"waves={w} xcd_run={x}"
-        if ref is None:
-            ref = (out.clone(), q.clone())
-        assert torch.equal(out, ref[0]) and torch.equal(q, ref[1]), f"waves={w} xcd_run={x}"
-    mesh.set_launch("fp64")
+    for mode in ("fp64", "fp32", "split_bf16"):
+        ref = None
+        for w, x in itertools.product((4, 2), (1, 2, 5)):
+            mesh.set_launch(mode, w, 1, 1, x)
+            out = torch.full_like(q0, float("nan"))
+            dg.rhs(mesh, q0, out, mode)
+            q = q0.clone()
+            work = torch.full((2,) + tuple(q.shape), float("nan"), dtype=torch.float64, device=dev)
+            for s in range(2):
+                dg.rk_step(mesh, q, work, s * dt, dt, mode)
+            torch.cuda.synchronize()
+            label = f"{mode} waves={w} xcd_run={x}"
+            assert not torch.isnan(out).any() and not torch.isnan(q).any(), label
+            if ref is None:
+                ref = (out.clone(), q.clone())
+            assert torch.equal(out, ref[0]) and torch.equal(q, ref[1]), label
+        mesh.set_launch(mode)
 
 
 def test_autotune_chooses_sets_and_caches(tmp_path):
@@ -329,7 +332,7 @@ def test_autotune_chooses_sets_and_caches(tmp_path):
     cfg, ms = mesh.autotune("split_bf16", cache_path=cache, trials=2)
     assert ms > 0 and cfg == mesh.get_launch("split_bf16")
     assert cfg["waves_per_block"] in (2, 4) and cfg["rk_fused"] in (0, 1) and cfg["lds_stage"] in (0, 1)
-    assert cfg["xcd_run"] == 1  # only the FP64 kernel takes XCD runs
+    assert cfg["xcd_run"] in (1, 9, 27)
     assert mesh.get_launch("fp64") == dict(waves_per_block=4, rk_fused=1, lds_stage=1, xcd_run=1)  # untouched
     import json
     (key, entry), = json.loads(cache.read_text())["entries"].items()
