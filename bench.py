@@ -409,6 +409,7 @@ def copy_bandwidth(dev, stream, mib: int = 1024, reps: int = 20):
     n = mib * (1 << 20) // 8
     src = torch.ones(n, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
+    torch.cuda.synchronize()  # src was filled on the default stream; the copies run on `stream`
     with torch.cuda.stream(stream):
         for _ in range(3):
             dst.copy_(src)
@@ -552,6 +553,7 @@ def learned_leg(dg, wl, dev, stream, X48):
             cnt += sl.numel()
         return acc / cnt
 
+    torch.cuda.synchronize()  # the training set and loss were made on the default stream
     t0 = time.perf_counter()
     epoch_loss = []
     with torch.cuda.stream(stream):
@@ -577,6 +579,7 @@ def learned_leg(dg, wl, dev, stream, X48):
     Tp, ip = torch.empty(n, dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.int32, device=dev)
     Tl, il = torch.empty_like(Tp), torch.empty_like(ip)
     fb = torch.zeros(1, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()  # fb was cleared on the default stream
     with torch.cuda.stream(stream):
         dg.temperature(th, q, Tp, ip, stream=stream)
         dg.temperature_learned(th, net, q, Tl, il, fallback_count=fb, stream=stream)
@@ -907,12 +910,15 @@ def main():
     if not args.no_rk:
         work = torch.empty((2,) + tuple(q.shape), dtype=torch.float64, device=dev)
         qs = q.clone()
+        torch.cuda.synchronize()  # qs was written on the default stream; the steps run on `stream`
         for mode in modes:
             t_rk, sp_rk = time_rk_step(dg, mesh, qs, work, 1e-4, mode, max(2, args.steps // 10), stream)
             (rec if mode == head else variants[mode])["lsrk_step_ms"] = round(t_rk, 4)
             (rec if mode == head else variants[mode])["lsrk_step_ms_spread"] = sp_rk
+        dg.synchronize(0, stream)  # raises if a step produced a non-finite state
         if len(modes) > 1 and args.long_steps > 0:
             rec["after_steps"] = long_run_errors(dg, mesh, q, q_np, work, modes, args.long_steps, stream)
+            dg.synchronize(0, stream)
         del work, qs
     if args.cpu_sample != 0:
         state = lambda Xn: wl.vortex_state(Xn, pert=wl.density_perturbation(WORKLOAD["pert_seed"]))
