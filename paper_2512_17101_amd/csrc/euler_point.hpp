@@ -63,12 +63,44 @@ __device__ inline void scaled_normal(int face, const double gm[9], double& Nx, d
   Nz = cr * gm[2] + cs * gm[5] + ct * gm[8];
 }
 
-// Scaled local Lax-Friedrichs jump at a face node, N = Fscale n, U_n = N . u:
-//   D = 1/2 (N.F(q-) - N.F(q+)) - 1/2 max(|U_n-| + c- |N|, |U_n+| + c+ |N|) (q- - q+).
+// The scaled normal of the face of face-node step s, where lane group g
+// takes face node 4 s + g of its element (NFP face nodes per face).  Where
+// the four groups sit on one face, which is known once the step loop is
+// unrolled, the normal is a metric row negated, or the sum of the three:
+// the same values as scaled_normal (up to the sign of a zero component)
+// without its multiplications by 0 and 1, which IEEE rules keep in the
+// code.  Steps that straddle two faces take scaled_normal.
+template <int NFP>
+__device__ inline void step_normal(int s, int face, const double gm[9], double& Nx, double& Ny, double& Nz) {
+  const int f0 = (4 * s) / NFP;
+  if (f0 == (4 * s + 3) / NFP) {
+    switch (f0) {
+      case 0: Nx = -gm[6]; Ny = -gm[7]; Nz = -gm[8]; break;
+      case 1: Nx = -gm[3]; Ny = -gm[4]; Nz = -gm[5]; break;
+      case 2:
+        Nx = (gm[0] + gm[3]) + gm[6];
+        Ny = (gm[1] + gm[4]) + gm[7];
+        Nz = (gm[2] + gm[5]) + gm[8];
+        break;
+      default: Nx = -gm[0]; Ny = -gm[1]; Nz = -gm[2]; break;
+    }
+  } else {
+    scaled_normal(face, gm, Nx, Ny, Nz);
+  }
+}
+
+// Twice the scaled local Lax-Friedrichs jump at a face node, N = Fscale n,
+// U_n = N . u:
+//   2 D = N.F(q-) - N.F(q+) - max(|U_n-| + c- |N|, |U_n+| + c+ |N|) (q- - q+).
+// The factor 1/2 is folded into the LIFT columns of the operator tables (a
+// power-of-two scaling, exact in every precision the tables are kept in, as
+// is the doubled jump's rounding to FP32 or BF16), so the contraction gives
+// the same products as with D and the unscaled LIFT.  The sound speed and
+// |N| enter through one root per side, c |N| = sqrt(gamma p / rho |N|^2).
 __device__ inline void lf_jump(const double qm[5], const double qp[5], double Nx, double Ny, double Nz,
                                double gamma, double D[5]) {
   const double gm1 = gamma - 1.0;
-  const double Fs = sqrt_pos(Nx * Nx + Ny * Ny + Nz * Nz);
+  const double N2 = Nx * Nx + Ny * Ny + Nz * Nz;
   const double irm = recip(qm[0]), irp = recip(qp[0]);
   const double um = qm[1] * irm, vm = qm[2] * irm, wm = qm[3] * irm;
   const double up = qp[1] * irp, vp = qp[2] * irp, wp = qp[3] * irp;
@@ -76,13 +108,13 @@ __device__ inline void lf_jump(const double qm[5], const double qp[5], double Nx
   const double pp = gm1 * (qp[4] - 0.5 * (qp[1] * up + qp[2] * vp + qp[3] * wp));
   const double Unm = Nx * um + Ny * vm + Nz * wm;
   const double Unp = Nx * up + Ny * vp + Nz * wp;
-  const double cm = sqrt_pos(gamma * pm * irm), cp = sqrt_pos(gamma * pp * irp);
-  const double lamFs = fmax(fabs(Unm) + cm * Fs, fabs(Unp) + cp * Fs);
-  D[0] = 0.5 * (qm[0] * Unm - qp[0] * Unp) - 0.5 * lamFs * (qm[0] - qp[0]);
-  D[1] = 0.5 * (qm[1] * Unm + pm * Nx - qp[1] * Unp - pp * Nx) - 0.5 * lamFs * (qm[1] - qp[1]);
-  D[2] = 0.5 * (qm[2] * Unm + pm * Ny - qp[2] * Unp - pp * Ny) - 0.5 * lamFs * (qm[2] - qp[2]);
-  D[3] = 0.5 * (qm[3] * Unm + pm * Nz - qp[3] * Unp - pp * Nz) - 0.5 * lamFs * (qm[3] - qp[3]);
-  D[4] = 0.5 * ((qm[4] + pm) * Unm - (qp[4] + pp) * Unp) - 0.5 * lamFs * (qm[4] - qp[4]);
+  const double cFm = sqrt_pos(gamma * pm * irm * N2), cFp = sqrt_pos(gamma * pp * irp * N2);
+  const double lamFs = fmax(fabs(Unm) + cFm, fabs(Unp) + cFp);
+  D[0] = (qm[0] * Unm - qp[0] * Unp) - lamFs * (qm[0] - qp[0]);
+  D[1] = (qm[1] * Unm + pm * Nx - qp[1] * Unp - pp * Nx) - lamFs * (qm[1] - qp[1]);
+  D[2] = (qm[2] * Unm + pm * Ny - qp[2] * Unp - pp * Ny) - lamFs * (qm[2] - qp[2]);
+  D[3] = (qm[3] * Unm + pm * Nz - qp[3] * Unp - pp * Nz) - lamFs * (qm[3] - qp[3]);
+  D[4] = ((qm[4] + pm) * Unm - (qp[4] + pp) * Unp) - lamFs * (qm[4] - qp[4]);
 }
 
 // Block renumbering for the 8 XCDs, which take workgroups round-robin and

@@ -249,7 +249,10 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
             qp[f] = q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
         }
         double Nx, Ny, Nz;
-        scaled_normal(face, gm, Nx, Ny, Nz);
+        if constexpr (FU == C::KL)
+          step_normal<C::NFP>(s, face, gm, Nx, Ny, Nz);  // s is a constant here
+        else
+          scaled_normal(face, gm, Nx, Ny, Nz);
         lf_jump(qm, qp, Nx, Ny, Nz, A.gamma, D);
 #pragma unroll
         for (int rb = 0; rb < C::NR; ++rb) mma(op[((3 * C::KV + s) * C::NR + rb) * 64 + lane], rb, D);
@@ -316,7 +319,7 @@ __device__ inline void lowp_tile(const LowArgs& A, const uint32_t* __restrict__ 
             qp[f] = q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
         }
         double Nx, Ny, Nz;
-        scaled_normal(face, gm, Nx, Ny, Nz);
+        step_normal<C::NFP>(t, face, gm, Nx, Ny, Nz);
         lf_jump(qm, qp, Nx, Ny, Nz, A.gamma, D);
 #pragma unroll
         for (int f = 0; f < 5; ++f) xf[f][t % 8] = static_cast<float>(D[f]);

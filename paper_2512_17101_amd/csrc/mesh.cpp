@@ -57,6 +57,8 @@ bool build_nbtab(const RefElem& R, std::vector<uint8_t>& tab) {
   return true;
 }
 
+// The FP64 contraction table [-Dr | -Ds | -Dt | LIFT / 2] in the kernel's
+// MFMA operand order (the face kernels contract twice the jump).
 void build_op64(const RefElem& R, const OpLayout& L, std::vector<double>& A) {
   const int Np = R.Np, Nfp = R.Nfp;
   const int K = 3 * L.NPP + 4 * Nfp;
@@ -65,7 +67,7 @@ void build_op64(const RefElem& R, const OpLayout& L, std::vector<double>& A) {
   for (int i = 0; i < Np; ++i) {
     for (int a = 0; a < 3; ++a)
       for (int j = 0; j < Np; ++j) Op[i * K + a * L.NPP + j] = -(*D[a])[i * Np + j];
-    for (int c = 0; c < 4 * Nfp; ++c) Op[i * K + 3 * L.NPP + c] = R.LIFT[i * 4 * Nfp + c];
+    for (int c = 0; c < 4 * Nfp; ++c) Op[i * K + 3 * L.NPP + c] = 0.5 * R.LIFT[i * 4 * Nfp + c];
   }
   A.assign(static_cast<size_t>(L.KS) * L.NRB * 64, 0.0);
   for (int ks = 0; ks < L.KS; ++ks)
@@ -91,7 +93,8 @@ float bf16_value(uint16_t h) {
   return x;
 }
 
-// Op[i][col] of [-Dr | -Ds | -Dt | LIFT] with each D block padded to NPP columns
+// Op[i][col] of [-Dr | -Ds | -Dt | LIFT / 2] with each D block padded to NPP
+// columns (the face kernels contract twice the Lax-Friedrichs jump)
 double op_entry(const RefElem& R, int NPP, int i, int col) {
   if (i >= R.Np) return 0.0;
   if (col < 3 * NPP) {
@@ -100,7 +103,7 @@ double op_entry(const RefElem& R, int NPP, int i, int col) {
     const std::vector<double>& D = a == 0 ? R.Dr : a == 1 ? R.Ds : R.Dt;
     return -D[i * R.Np + j];
   }
-  return R.LIFT[i * 4 * R.Nfp + (col - 3 * NPP)];
+  return 0.5 * R.LIFT[i * 4 * R.Nfp + (col - 3 * NPP)];
 }
 
 void build_lowp_tables(const RefElem& R, std::vector<float>& op32, std::vector<uint16_t>& opbf) {

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(P >= 4 ?
                       : q[f * Es + static_cast<int64_t>(c.x) * C::NP + jp];
     }
     double Nx, Ny, Nz, D[5];
-    scaled_normal(face, gm, Nx, Ny, Nz);
+    step_normal<C::NFP>(s, face, gm, Nx, Ny, Nz);
     lf_jump(qm, qp, Nx, Ny, Nz, A.gamma, D);
 #pragma unroll
     for (int rb = 0; rb < C::NRB; ++rb) {
