@@ -14,6 +14,10 @@ namespace {
 
 bool valid_prec(dg_precision p) { return p == DG_FP64 || p == DG_FP32 || p == DG_SPLIT_BF16; }
 
+// a cached field that converts to int without overflow (0 .. 64 covers
+// every valid value; anything else is rejected before the conversion)
+bool in_int_range(double v) { return v >= 0.0 && v <= 64.0; }
+
 bool valid_launch(const dg_launch_config& c) {
   return (c.waves_per_block == 2 || c.waves_per_block == 4) && (c.rk_fused == 0 || c.rk_fused == 1) &&
          (c.lds_stage == 0 || c.lds_stage == 1) && c.xcd_run >= 1 && c.xcd_run <= 64;
@@ -59,7 +63,8 @@ extern "C" dg_status dg_autotune(dg_mesh h, const dg_params* prm, dg_precision p
     const auto it = cache.find(key);
     double w, f, l, x;
     if (it != cache.end() && cache_field(it->second, "waves_per_block", w) && cache_field(it->second, "rk_fused", f) &&
-        cache_field(it->second, "lds_stage", l) && cache_field(it->second, "xcd_run", x)) {
+        cache_field(it->second, "lds_stage", l) && cache_field(it->second, "xcd_run", x) &&
+        in_int_range(w) && in_int_range(f) && in_int_range(l) && in_int_range(x)) {
       const dg_launch_config c{static_cast<int>(w), static_cast<int>(f), static_cast<int>(l), static_cast<int>(x)};
       if (valid_launch(c)) {
         m.launch[prec] = c;
