@@ -138,8 +138,10 @@ def test_rhs_full_size_p3_48cubed():
     the launch configuration the benchmark times, every entry of the whole
     mesh against the oracle (evaluated in chunks of elements)."""
     _dev()
+    import bench
     xyz, vid = wl.kuhn_box_mesh(48, 10.0, 0.03, 1002)
     mesh = dg.Mesh(3, xyz, vid)
+    mesh.set_launch("fp64", *bench.parse_launch(bench.DEFAULT_LAUNCH))
     ops = ore.operators(3)
     q_np = wl.vortex_state(om.node_coordinates(xyz, ops["rst"]), pert=wl.density_perturbation(2002))
     got = _gpu_rhs(mesh, q_np)
