@@ -93,6 +93,14 @@ def test_stored_counters_follow_the_launch_shape(tmp_path, monkeypatch):
         assert bench.stored_counters(dict(same, **{k: v})) == {}, k
 
 
+def test_launch_option_parses_four_integers():
+    assert bench.parse_launch(bench.DEFAULT_LAUNCH) == [4, 1, 1, 27]
+    assert bench.parse_launch("2,0,1,9") == [2, 0, 1, 9]
+    for bad in ("4,1,1", "4,1,1,27,3", "a,b,c,d"):
+        with pytest.raises(ValueError):
+            bench.parse_launch(bad)
+
+
 def test_committed_counter_summary_matches_the_sources():
     """The committed FP64 counter summary was taken on the current kernel
     sources (else the bench line would report no traffic)."""
