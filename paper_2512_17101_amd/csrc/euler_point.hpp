@@ -124,8 +124,9 @@ __device__ inline void lf_jump(const double qm[5], const double qp[5], double Nx
 // Blocks past the last whole run keep the plain order; a bijection of
 // [0, nblocks) for every k >= 1.
 __device__ inline int xcd_run_block(int blk, int nblocks, int k) {
+  if (k <= 1) return blk;  // also guards the divisions below
   const int full = nblocks / (8 * k) * (8 * k);
-  if (k <= 1 || blk >= full) return blk;
+  if (blk >= full) return blk;
   const int i = blk >> 3;
   return ((i / k) * 8 + (blk & 7)) * k + i % k;
 }
